@@ -1,0 +1,57 @@
+"""The seeded input generator: vectorised backends agree bit for bit with the scalar
+definition, limbs are non-overlapping by construction, and the recipes have the stated
+structure."""
+import math
+
+import numpy as np
+import pytest
+
+import mdgen
+
+
+def test_uniform_matches_scalar_definition():
+    v = mdgen.uniform(12345, 3, 50, k0=7)
+    for i in range(50):
+        assert v[i] == mdgen.uniform_scalar(12345, 3, 7 + i)
+    assert np.all(v >= -1.0) and np.all(v < 1.0)
+
+
+def test_torch_backend_bit_identical():
+    torch = pytest.importorskip("torch")
+    for P in (1, 2, 4, 8):
+        a = mdgen.md_uniform(P, 33, 17, 99, mdgen.STREAM_A)
+        t = mdgen.md_uniform(P, 33, 17, 99, mdgen.STREAM_A, device="cpu").numpy()
+        assert np.array_equal(a, t)
+    U = mdgen.upper_triangular(4, 20, 5, well_conditioned=True)
+    Ut = mdgen.upper_triangular(4, 20, 5, well_conditioned=True, device="cpu").numpy()
+    assert np.array_equal(U, Ut)
+
+
+@pytest.mark.parametrize("P", (2, 4, 8))
+def test_limbs_nonoverlapping(P):
+    a = mdgen.md_uniform(P, 64, 64, 1, mdgen.STREAM_A).reshape(P, -1)
+    for k in range(1, P):
+        hi, lo = a[k - 1], a[k]
+        nz = hi != 0
+        ulp = np.array([math.ulp(x) for x in hi[nz]])
+        assert np.all(np.abs(lo[nz]) <= ulp / 2)
+        assert np.all(lo[~nz] == 0.0)
+
+
+def test_upper_triangular_structure():
+    n = 40
+    U = mdgen.upper_triangular(2, n, 3)
+    lead = U[0].T  # rows x cols
+    assert np.all(np.tril(lead, -1) == 0.0)
+    d = np.diag(lead)
+    assert np.all((d >= 1.0) & (d <= 2.0))
+    W = mdgen.upper_triangular(2, n, 3, well_conditioned=True)
+    off = np.triu(W[0].T, 1)
+    assert np.max(np.abs(off)) <= 2.0 ** -math.ceil(math.log2(n))
+
+
+def test_batch_shapes_ranges():
+    sh = mdgen.batch_shapes(512, 4)
+    assert len(sh) == 512
+    for m, n in sh:
+        assert 32 <= m <= 512 and 16 <= n <= m
