@@ -1,0 +1,206 @@
+#!/usr/bin/env python3
+"""Benchmark of the multiple-double least-squares hot path on one MI355X.
+
+One step solves the square n = 1024 least-squares problem (tile 128) once in double double,
+once in quad double and once in octo double: blocked Householder QR with Q^T b folded in,
+then the tiled back substitution (paper Algorithms 2 and 1, Section 4 Table 11 workload).
+Inputs are seeded synthetic matrices generated directly in device memory; every step
+restores the pristine A and b (device-to-device copies of 16 + 32 + 64 MiB) before solving.
+
+``value`` is the paper's throughput measure: the algorithmic double-operation count of the
+three solves (Table 1 weights, see paper_2110_08375_amd/opcount.py) divided by the wall time
+of the step, in TFLOP/s.  The JSON line also carries, per precision, the solve time and its
+fraction of the FP64 peak; a roofline entry for the kernel that takes the most device time
+(per-kernel HIP-event timing inside the library, on the solve's stream); and the CPU oracle
+timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "double-op TFLOP/s QR+backsub n=1024 dd/qd/od vs FP64 peak; batched solves/s"
+PNAME = {1: "d", 2: "dd", 4: "qd", 8: "od"}
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def make_problem(P, m, n, seed, device):
+    import mdgen
+
+    A = mdgen.md_uniform(P, m, n, seed, mdgen.STREAM_A, device=device).contiguous()
+    b = mdgen.md_vector(P, m, seed, mdgen.STREAM_B, device=device).contiguous()
+    return A, b
+
+
+def cpu_baseline(sample, threads):
+    """The CPU oracle (unchanged) on a bounded sample; Table-1 double ops per second."""
+    import mdgen
+    import oracle
+    from paper_2110_08375_amd import opcount
+
+    total_ops, total_s = 0.0, 0.0
+    for P, n in sample:
+        A, _ = mdgen.ls_problem(P, n, n, 3)
+        b = mdgen.md_vector(P, n, 3, mdgen.STREAM_B)
+        t0 = time.perf_counter()
+        oracle.lstsq(A, b, nthreads=threads)
+        dt = time.perf_counter() - t0
+        total_s += dt
+        total_ops += opcount.ls_double_ops(P, n, n)
+        log("cpu oracle %s n=%d: %.2f s" % (PNAME[P], n, dt))
+    return total_ops / total_s / 1e12, total_s
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--m", type=int, default=1024)
+    ap.add_argument("--n", type=int, default=1024)
+    ap.add_argument("--tile", type=int, default=128)
+    ap.add_argument("--precisions", default="2,4,8", help="limb counts, e.g. 2,4,8")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-kernel-timing", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the design for sharding is described in DESIGN.md); run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2110_08375_amd as M
+    from paper_2110_08375_amd import opcount
+
+    M.lib()
+    dev = torch.device("cuda:0")
+    m, n, tile = args.m, args.n, args.tile
+    precs = [int(p) for p in args.precisions.split(",")]
+    log("device %s, m=%d n=%d tile=%d precisions=%s" % (torch.cuda.get_device_name(0), m, n, tile, precs))
+
+    prob = {}
+    for P in precs:
+        A0, b0 = make_problem(P, m, n, 7000 + P, dev)
+        prob[P] = dict(A0=A0, b0=b0, A=torch.empty_like(A0), b=torch.empty_like(b0),
+                       x=torch.empty((P, n), dtype=torch.float64, device=dev),
+                       ws=M.workspace(P, m, n, tile, dev),
+                       info=torch.zeros(1, dtype=torch.int32, device=dev))
+    torch.cuda.synchronize()
+
+    def step(events=None):
+        for P in precs:
+            d = prob[P]
+            d["A"].copy_(d["A0"])
+            d["b"].copy_(d["b0"])
+            if events is not None:
+                events[P][0].record()
+            M.solve(P, d["A"], d["b"], tile, x=d["x"], ws=d["ws"], info=d["info"])
+            if events is not None:
+                events[P][1].record()
+
+    for w in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log("warmup step %d done" % (w + 1))
+    for P in precs:
+        if int(prob[P]["info"].item()) != 0:
+            raise RuntimeError("solve reported info=%d for %s" % (int(prob[P]["info"].item()), PNAME[P]))
+
+    per_ms = {P: 0.0 for P in precs}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        ev = {P: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for P in precs}
+        step(ev)
+        torch.cuda.synchronize()
+        for P in precs:
+            per_ms[P] += ev[P][0].elapsed_time(ev[P][1])
+        log("timed step %d done" % (s + 1))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall * 1e3 / args.steps
+    ops_step = sum(opcount.ls_double_ops(P, m, n) for P in precs)
+    value = ops_step / (ms_per_step * 1e-3) / 1e12
+    peak = opcount.FP64_PEAK_TFLOPS
+
+    per_prec = {}
+    for P in precs:
+        ms = per_ms[P] / args.steps
+        tf = opcount.ls_double_ops(P, m, n) / (ms * 1e-3) / 1e12
+        per_prec[PNAME[P]] = {"ms": round(ms, 4), "tflops": round(tf, 4), "frac_fp64_peak": round(tf / peak, 5),
+                              "solves_per_s": round(1e3 / ms, 3)}
+        log("%s: %.3f ms per solve, %.3f TFLOP/s" % (PNAME[P], ms, tf))
+
+    roof = None
+    if not args.no_kernel_timing:
+        M.timing_reset()
+        M.timing_enable(True)
+        step()
+        torch.cuda.synchronize()
+        M.timing_enable(False)
+        best = None
+        kernels = {}
+        for name in M.timing_kernels():
+            for P in precs:
+                ms, cnt, work = M.timing_query(name, P)
+                if cnt == 0:
+                    continue
+                kernels["%s<%s>" % (name, PNAME[P])] = {"ms": round(ms, 4), "launches": cnt,
+                                                        "avg_us": round(ms * 1e3 / cnt, 3)}
+                if best is None or ms > best[1]:
+                    best = (name, ms, cnt, work, P)
+        M.timing_reset()
+        name, ms, cnt, work, P = best
+        achieved = work * opcount.md_fma_double_ops(P) / (ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "kernel": "%s<%s>" % (name, PNAME[P]), "achieved": round(achieved, 4),
+                "peak": round(peak, 2), "unit": "TFLOP/s", "frac": round(achieved / peak, 5), "traffic": None,
+                "launches": cnt, "avg_launch_us": round(ms * 1e3 / cnt, 3),
+                "per_kernel": kernels}
+        log("dominant kernel %s<%s>: %.3f ms over %d launches, %.3f TFLOP/s" % (name, PNAME[P], ms, cnt, achieved))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        sample = [(2, 384), (4, 192), (8, 96)]
+        v, secs = cpu_baseline(sample, threads)
+        cpu = {"value": v, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
+               "sample": "oracle least squares (unblocked Householder QR + Q^T b + back substitution) on square "
+                         "dd n=384, qd n=192, od n=96 with the same input recipe; %.1f s" % secs}
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 5),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "least squares, square m=n=%d, tile %d, one solve each in %s" %
+                                (n, tile, "/".join(PNAME[P] for P in precs)),
+                   "m": m, "n": n, "tile": tile, "precisions": [PNAME[P] for P in precs]},
+        "per_precision": per_prec,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

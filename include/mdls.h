@@ -1,0 +1,133 @@
+/*
+ * mdls.h -- multiple-double least squares on AMD MI355X (gfx950): the C ABI.
+ *
+ * Solves min || b - A x ||_2 for a full-column-rank A (m x n, m >= n) in double double,
+ * quad double or octo double arithmetic: numbers are unevaluated sums of P = 2, 4 or 8
+ * doubles (paper Section 1.1).  The method is the paper's: Householder QR of A (Section 3,
+ * Algorithm 2, with the sign choice of Golub and Van Loan Algorithm 5.1.1), the product
+ * Q^T b, and the tiled back substitution of R x = Q^T b (Section 2, Algorithm 1: invert the
+ * diagonal tiles, then alternate x_i = U_i^{-1} b_i with the updates b_j -= A_{j,i} x_i).
+ *
+ * Storage (the paper's staging, end of Section 2): a matrix of multiple doubles is P planes
+ * of doubles, most significant limb first.  Plane k starts ld * cols doubles after plane
+ * k - 1 and is column-major with leading dimension ld >= rows.  A vector of length L is P
+ * planes of L doubles.  Every pointer below is a DEVICE pointer.  The caller owns every
+ * buffer; the library never allocates, frees or synchronises, and enqueues all work on the
+ * caller's stream, so a call sequence can be captured into a HIP graph.
+ *
+ * Errors: a call returns 0 on success; -i when argument i (1-based) is invalid, checked on
+ * the host before anything is enqueued (LAPACK convention); MDLS_EHIP when a launch fails.
+ * Numerical status is written asynchronously to the device int *d_info where a call has
+ * one: 0 = success, k > 0 = R(k,k) is exactly zero (1-based), x then unspecified.
+ * NaN and Inf in the input propagate to the output unchecked.  No call throws.
+ *
+ * Threading: calls on distinct streams with distinct buffers and workspaces may run
+ * concurrently.  One workspace must not be used by two calls in flight at once.
+ */
+#ifndef MDLS_H
+#define MDLS_H
+
+#include <stddef.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* precision = number of limbs P.  MDLS_F64 (one limb) exists for tests only. */
+typedef enum { MDLS_F64 = 1, MDLS_DD = 2, MDLS_QD = 4, MDLS_OD = 8 } mdls_prec;
+
+#define MDLS_EHIP (-100)        /* a kernel launch failed */
+#define MDLS_EUNSUPPORTED (-101) /* valid arguments outside what this build handles */
+
+/* Largest number of rows the Householder panel kernel holds on chip, for precision p. */
+int mdls_max_rows(int p);
+
+/*
+ * Bytes of device workspace that mdls_qr, mdls_apply_qt, mdls_backsub and mdls_solve need
+ * for (p, m, n, tile).  The same workspace serves all four.  Returns 0 for invalid input.
+ */
+size_t mdls_workspace_bytes(int p, int m, int n, int tile);
+
+/*
+ * Householder QR (paper Algorithm 2).  A (m x n, lda >= m) is overwritten: R in the upper
+ * triangle, the Householder vector v_j of column j below the diagonal (v_j has a unit
+ * first entry that is not stored; v_j and beta_j as in Golub-Van Loan Algorithm 5.1.1, so
+ * R(j,j) >= 0 whenever the column below the diagonal is not exactly zero, and beta_j = 0
+ * with R(j,j) unchanged when it is).
+ * T (may be NULL): P planes of ldt x n, ldt >= tile.  For each tile block k (columns
+ * k*tile .. k*tile+tile-1) rows 0..tile-1 of those columns receive the upper-triangular
+ * tile x tile factor T_k with H_{k*tile} ... H_{k*tile+tile-1} = I - Y_k T_k Y_k^T, Y_k the
+ * unit lower trapezoidal block of Householder vectors; diag(T_k) holds the beta_j.  The
+ * paper's W of P_WY = I + W Y^T is W_k = -Y_k T_k (see mdls_form_w).
+ * Requires n % tile == 0 when T != NULL, and m <= mdls_max_rows(p).
+ */
+int mdls_qr(int p, int m, int n, int tile, double *A, int lda, double *T, int ldt, void *ws,
+            size_t ws_bytes, hipStream_t stream);
+
+/*
+ * B := Q^T B with Q = H_0 H_1 ... H_{n-1} from mdls_qr (paper Section 1: A x = b becomes
+ * R x = Q^T b).  A and T as returned by mdls_qr with the same tile.  B is m x nrhs
+ * (ldb >= m).  Applies the tile blocks in order: B := (I - Y_k T_k^T Y_k^T) B, which is
+ * the paper's B + Y_k (W_k^T B).
+ */
+int mdls_apply_qt(int p, int m, int n, int tile, const double *A, int lda, const double *T,
+                  int ldt, double *B, int ldb, int nrhs, void *ws, size_t ws_bytes,
+                  hipStream_t stream);
+
+/*
+ * The paper's W factor (Section 3, eqs. for P_WY = I + W Y^T): W_k = -Y_k T_k for every
+ * tile block, written to W (P planes of ldw x n, ldw >= m): block k occupies columns
+ * k*tile.. and rows k*tile..m-1; rows above are set to zero.
+ */
+int mdls_form_w(int p, int m, int n, int tile, const double *A, int lda, const double *T,
+                int ldt, double *W, int ldw, hipStream_t stream);
+
+/*
+ * Tiled back substitution (paper Algorithm 1): solves R x = y with R the upper triangle of
+ * the leading n x n block of R (ldr >= n, entries below the diagonal are not read), n a
+ * multiple of tile.  x holds y on entry (P planes of n doubles) and the solution on exit.
+ * Stage 1 inverts the n/tile diagonal tiles, stage 2 alternates x_i := U_i^{-1} b_i with
+ * b_j -= A_{j,i} x_i for j < i.  *d_info as described above.
+ */
+int mdls_backsub(int p, int n, int tile, const double *R, int ldr, double *x, void *ws,
+                 size_t ws_bytes, int *d_info, hipStream_t stream);
+
+/*
+ * Least squares: A (m x n) and b (P planes of m) are overwritten by the factors and by
+ * Q^T b; x (P planes of n) receives the solution of R x = (Q^T b)(0:n).  tile is the back
+ * substitution tile (n % tile == 0).  *d_info as above.
+ */
+int mdls_solve(int p, int m, int n, int tile, double *A, int lda, double *b, double *x,
+               void *ws, size_t ws_bytes, int *d_info, hipStream_t stream);
+
+/* Static text for a status code. */
+const char *mdls_status_string(int status);
+
+/*
+ * Per-kernel device timing, as the paper reports per-kernel times (Section 4, kernel time
+ * versus wall time).  While enabled, every kernel the library launches is bracketed by two
+ * HIP events recorded on the caller's stream, and recorded with its name, its precision P
+ * and its algorithmic multiple-double multiply-add count.  Host-side state shared by all
+ * threads of the process; meant for benchmarks, not for concurrent production calls.
+ *   mdls_timing_enable(on)    start (on != 0) or stop recording; returns 0.
+ *   mdls_timing_reset()       wait for and discard all records; returns 0.
+ *   mdls_timing_query(name, p, &ms, &launches, &md_fmas)
+ *                             waits for the recorded events and sums the launches of kernel
+ *                             `name` ("" = all kernels) at precision p (0 = all); returns 0,
+ *                             -i for a null argument i, MDLS_EHIP on an event error.
+ *   mdls_timing_kernels(buf, len)
+ *                             newline-separated names of the kernels recorded so far
+ *                             (truncated to len - 1 bytes); returns the number of names.
+ */
+int mdls_timing_enable(int on);
+int mdls_timing_reset(void);
+int mdls_timing_query(const char *name, int p, double *total_ms, long *launches, double *md_fmas);
+int mdls_timing_kernels(char *buf, int buflen);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MDLS_H */

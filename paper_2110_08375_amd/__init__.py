@@ -1,0 +1,22 @@
+"""Multiple-double least squares on AMD MI355X (gfx950).
+
+The compute path is the HIP library ``libmdls.so`` (built from ``csrc/`` by ``build.py``) behind
+the C ABI of ``include/mdls.h``; :mod:`paper_2110_08375_amd.mdls` is a thin ctypes binding with
+the same names that only marshals arguments.  PyTorch supplies device memory and streams.
+"""
+from .mdls import (  # noqa: F401
+    MDLS_DD,
+    MDLS_F64,
+    MDLS_OD,
+    MDLS_QD,
+    apply_qt,
+    backsub,
+    form_w,
+    lib,
+    max_rows,
+    qr,
+    solve,
+    status_string,
+    workspace,
+    workspace_bytes,
+)

@@ -1,0 +1,277 @@
+// mdls_capi.hip -- the C ABI declared in mdls.h: argument checks on the host, then the
+// per-precision drivers (instantiated in mdls_p1/2/4/8.hip).
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "mdls_impl.hpp"
+
+namespace mdls_impl {
+MDLS_FOR_PRECISION(extern, 1)
+MDLS_FOR_PRECISION(extern, 2)
+MDLS_FOR_PRECISION(extern, 4)
+MDLS_FOR_PRECISION(extern, 8)
+}  // namespace mdls_impl
+
+using namespace mdls_impl;
+
+// ============================================================================ launch timing
+namespace {
+struct Timed {
+    std::string name;
+    int P;
+    double work;
+    hipEvent_t a, b;
+};
+std::mutex g_mu;
+bool g_on = false;
+std::vector<Timed> g_rec;
+std::vector<hipEvent_t> g_pool;
+
+hipEvent_t pool_get()
+{
+    if (!g_pool.empty()) {
+        hipEvent_t e = g_pool.back();
+        g_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+}  // namespace
+
+namespace mdls_impl {
+bool timing_on() { return g_on; }
+
+void timing_begin(hipStream_t s, void **ev)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    hipEvent_t e = pool_get();
+    if (e) hipEventRecord(e, s);
+    *ev = (void *)e;
+}
+
+void timing_end(hipStream_t s, void *ev, const char *name, int P, double work)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    hipEvent_t e = pool_get();
+    if (!ev || !e) return;
+    hipEventRecord(e, s);
+    g_rec.push_back(Timed{std::string(name), P, work, (hipEvent_t)ev, e});
+}
+}  // namespace mdls_impl
+
+namespace {
+template <template <int> class F, typename... Args>
+int dispatch(int p, Args... args)
+{
+    switch (p) {
+    case 1: return F<1>::run(args...);
+    case 2: return F<2>::run(args...);
+    case 4: return F<4>::run(args...);
+    case 8: return F<8>::run(args...);
+    }
+    return -1;
+}
+
+template <int P>
+struct SolveF {
+    template <typename... A>
+    static int run(A... a) { return solve_t<P>(a...); }
+};
+template <int P>
+struct QrF {
+    template <typename... A>
+    static int run(A... a) { return qr_t<P>(a...); }
+};
+template <int P>
+struct ApplyF {
+    template <typename... A>
+    static int run(A... a) { return apply_qt_t<P>(a...); }
+};
+template <int P>
+struct FormWF {
+    template <typename... A>
+    static int run(A... a) { return form_w_t<P>(a...); }
+};
+template <int P>
+struct BacksubF {
+    template <typename... A>
+    static int run(A... a) { return backsub_t<P>(a...); }
+};
+
+}  // namespace
+
+// ============================================================================ C ABI
+extern "C" {
+
+int mdls_max_rows(int p)
+{
+    if (!valid_p(p)) return 0;
+    return kGMax * kThreads * panel_rows_per_thread(p);
+}
+
+size_t mdls_workspace_bytes(int p, int m, int n, int tile)
+{
+    if (!valid_p(p) || n < 1 || m < n || !valid_tile(tile)) return 0;
+    return layout(p, m, n, tile).total;
+}
+
+int mdls_qr(int p, int m, int n, int tile, double *A, int lda, double *T, int ldt, void *ws, size_t ws_bytes,
+            hipStream_t stream)
+{
+    if (!valid_p(p)) return -1;
+    if (m < 1) return -2;
+    if (n < 1 || n > m) return -3;
+    if (!valid_tile(tile) || (T && n % tile != 0)) return -4;
+    if (!A) return -5;
+    if (lda < m) return -6;
+    if (T && ldt < tile) return -8;
+    if (!ws) return -9;
+    if (ws_bytes < mdls_workspace_bytes(p, m, n, tile)) return -10;
+    if (m > mdls_max_rows(p)) return MDLS_EUNSUPPORTED;
+    return dispatch<QrF>(p, m, n, tile, A, lda, T, ldt, ws, stream);
+}
+
+int mdls_apply_qt(int p, int m, int n, int tile, const double *A, int lda, const double *T, int ldt, double *B,
+                  int ldb, int nrhs, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    if (!valid_p(p)) return -1;
+    if (m < 1) return -2;
+    if (n < 1 || n > m) return -3;
+    if (!valid_tile(tile) || n % tile != 0) return -4;
+    if (!A) return -5;
+    if (lda < m) return -6;
+    if (!T) return -7;
+    if (ldt < tile) return -8;
+    if (!B && nrhs > 0) return -9;
+    if (ldb < m) return -10;
+    if (nrhs < 0) return -11;
+    if (!ws) return -12;
+    if (ws_bytes < mdls_workspace_bytes(p, m, n, tile)) return -13;
+    if (nrhs == 0) return 0;
+    return dispatch<ApplyF>(p, m, n, tile, A, lda, T, ldt, B, ldb, nrhs, ws, stream);
+}
+
+int mdls_form_w(int p, int m, int n, int tile, const double *A, int lda, const double *T, int ldt, double *W, int ldw,
+                hipStream_t stream)
+{
+    if (!valid_p(p)) return -1;
+    if (m < 1) return -2;
+    if (n < 1 || n > m) return -3;
+    if (!valid_tile(tile) || n % tile != 0) return -4;
+    if (!A) return -5;
+    if (lda < m) return -6;
+    if (!T) return -7;
+    if (ldt < tile) return -8;
+    if (!W) return -9;
+    if (ldw < m) return -10;
+    return dispatch<FormWF>(p, m, n, tile, A, lda, T, ldt, W, ldw, stream);
+}
+
+int mdls_backsub(int p, int n, int tile, const double *R, int ldr, double *x, void *ws, size_t ws_bytes, int *d_info,
+                 hipStream_t stream)
+{
+    if (!valid_p(p)) return -1;
+    if (n < 1) return -2;
+    if (!valid_tile(tile) || n % tile != 0) return -3;
+    if (!R) return -4;
+    if (ldr < n) return -5;
+    if (!x) return -6;
+    if (!ws) return -7;
+    if (ws_bytes < mdls_workspace_bytes(p, n, n, tile)) return -8;
+    if (!d_info) return -9;
+    return dispatch<BacksubF>(p, n, tile, R, ldr, x, ws, d_info, stream);
+}
+
+int mdls_solve(int p, int m, int n, int tile, double *A, int lda, double *b, double *x, void *ws, size_t ws_bytes,
+               int *d_info, hipStream_t stream)
+{
+    if (!valid_p(p)) return -1;
+    if (m < 1) return -2;
+    if (n < 1 || n > m) return -3;
+    if (!valid_tile(tile) || n % tile != 0) return -4;
+    if (!A) return -5;
+    if (lda < m) return -6;
+    if (!b) return -7;
+    if (!x) return -8;
+    if (!ws) return -9;
+    if (ws_bytes < mdls_workspace_bytes(p, m, n, tile)) return -10;
+    if (!d_info) return -11;
+    if (m > mdls_max_rows(p)) return MDLS_EUNSUPPORTED;
+    return dispatch<SolveF>(p, m, n, tile, A, lda, b, x, ws, d_info, stream);
+}
+
+int mdls_timing_enable(int on)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_on = on != 0;
+    return 0;
+}
+
+int mdls_timing_reset(void)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (auto &t : g_rec) {
+        hipEventSynchronize(t.b);
+        g_pool.push_back(t.a);
+        g_pool.push_back(t.b);
+    }
+    g_rec.clear();
+    return 0;
+}
+
+int mdls_timing_query(const char *name, int p, double *total_ms, long *launches, double *md_fmas)
+{
+    if (!name) return -1;
+    if (!total_ms) return -3;
+    if (!launches) return -4;
+    if (!md_fmas) return -5;
+    std::lock_guard<std::mutex> lk(g_mu);
+    double ms = 0.0, work = 0.0;
+    long cnt = 0;
+    for (auto &t : g_rec) {
+        if (name[0] && t.name != name) continue;
+        if (p && t.P != p) continue;
+        if (hipEventSynchronize(t.b) != hipSuccess) return MDLS_EHIP;
+        float e = 0.f;
+        if (hipEventElapsedTime(&e, t.a, t.b) != hipSuccess) return MDLS_EHIP;
+        ms += e;
+        work += t.work;
+        ++cnt;
+    }
+    *total_ms = ms;
+    *launches = cnt;
+    *md_fmas = work;
+    return 0;
+}
+
+int mdls_timing_kernels(char *buf, int buflen)
+{
+    if (!buf || buflen < 1) return -1;
+    std::lock_guard<std::mutex> lk(g_mu);
+    std::vector<std::string> names;
+    for (auto &t : g_rec) {
+        bool seen = false;
+        for (auto &n : names) seen = seen || (n == t.name);
+        if (!seen) names.push_back(t.name);
+    }
+    std::string out;
+    for (auto &n : names) out += n + "\n";
+    std::strncpy(buf, out.c_str(), (size_t)buflen - 1);
+    buf[buflen - 1] = 0;
+    return (int)names.size();
+}
+
+const char *mdls_status_string(int status)
+{
+    if (status == 0) return "success";
+    if (status == MDLS_EHIP) return "a HIP kernel launch failed";
+    if (status == MDLS_EUNSUPPORTED) return "arguments valid but outside what this build supports";
+    if (status < 0 && status > -20) return "invalid argument (the negated status is its 1-based position)";
+    return "unknown status";
+}
+
+}  // extern "C"

@@ -1,0 +1,6 @@
+// mdls_p2.hip -- kernels and drivers instantiated for 2-limb numbers.
+#include "mdls_impl.hpp"
+
+namespace mdls_impl {
+MDLS_FOR_PRECISION(, 2)
+}  // namespace mdls_impl

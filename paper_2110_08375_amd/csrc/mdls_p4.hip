@@ -1,0 +1,6 @@
+// mdls_p4.hip -- kernels and drivers instantiated for 4-limb numbers.
+#include "mdls_impl.hpp"
+
+namespace mdls_impl {
+MDLS_FOR_PRECISION(, 4)
+}  // namespace mdls_impl

@@ -1,0 +1,211 @@
+"""ctypes binding of the C ABI in ``include/mdls.h`` (argument marshalling only).
+
+Tensors follow the library's storage: a matrix of P-limb numbers with ``rows`` rows and
+``cols`` columns is a contiguous ``torch.float64`` tensor of shape ``(P, cols, rows)`` on the
+GPU (P column-major planes, leading dimension ``rows``); a vector is ``(P, length)``.  Every
+call is enqueued on the current torch stream.  Nothing here computes: if the HIP library is
+missing or cannot be loaded, every entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libmdls.so")
+
+MDLS_F64, MDLS_DD, MDLS_QD, MDLS_OD = 1, 2, 4, 8
+MDLS_EHIP, MDLS_EUNSUPPORTED = -100, -101
+
+# every symbol include/mdls.h declares
+EXPORTS = ("mdls_max_rows", "mdls_workspace_bytes", "mdls_qr", "mdls_apply_qt", "mdls_form_w",
+           "mdls_backsub", "mdls_solve", "mdls_status_string", "mdls_timing_enable", "mdls_timing_reset",
+           "mdls_timing_query", "mdls_timing_kernels")
+
+_lib = None
+
+
+class MdlsError(RuntimeError):
+    pass
+
+
+def lib():
+    """Load ``libmdls.so``; raise if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise MdlsError("libmdls.so is not built (run paper_2110_08375_amd/build.py); "
+                            "there is no CPU fallback")
+        L = ctypes.CDLL(_LIB_PATH)
+        i, sz, vp = ctypes.c_int, ctypes.c_size_t, ctypes.c_void_p
+        L.mdls_max_rows.argtypes = [i]
+        L.mdls_max_rows.restype = i
+        L.mdls_workspace_bytes.argtypes = [i, i, i, i]
+        L.mdls_workspace_bytes.restype = sz
+        L.mdls_qr.argtypes = [i, i, i, i, vp, i, vp, i, vp, sz, vp]
+        L.mdls_apply_qt.argtypes = [i, i, i, i, vp, i, vp, i, vp, i, i, vp, sz, vp]
+        L.mdls_form_w.argtypes = [i, i, i, i, vp, i, vp, i, vp, i, vp]
+        L.mdls_backsub.argtypes = [i, i, i, vp, i, vp, vp, sz, vp, vp]
+        L.mdls_solve.argtypes = [i, i, i, i, vp, i, vp, vp, vp, sz, vp, vp]
+        L.mdls_status_string.argtypes = [i]
+        L.mdls_status_string.restype = ctypes.c_char_p
+        L.mdls_timing_enable.argtypes = [i]
+        L.mdls_timing_reset.argtypes = []
+        L.mdls_timing_query.argtypes = [ctypes.c_char_p, i, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_long), ctypes.POINTER(ctypes.c_double)]
+        L.mdls_timing_kernels.argtypes = [ctypes.c_char_p, i]
+        for f in ("mdls_qr", "mdls_apply_qt", "mdls_form_w", "mdls_backsub", "mdls_solve", "mdls_timing_enable",
+                  "mdls_timing_reset", "mdls_timing_query", "mdls_timing_kernels"):
+            getattr(L, f).restype = i
+        _lib = L
+    return _lib
+
+
+def status_string(status: int) -> str:
+    return lib().mdls_status_string(status).decode()
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise MdlsError("%s failed with status %d (%s)" % (what, rc, status_string(rc)))
+
+
+def _stream():
+    import torch
+
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _mat(t, P, name):
+    import torch
+
+    if t.dtype != torch.float64 or not t.is_contiguous() or t.dim() != 3 or t.shape[0] != P:
+        raise ValueError("%s must be a contiguous float64 tensor of shape (P, cols, rows)" % name)
+    if not t.is_cuda:
+        raise ValueError("%s must live on the GPU" % name)
+    return t.shape[2], t.shape[1]  # rows (= ld), cols
+
+
+def _vec(t, P, name, length):
+    import torch
+
+    if (t.dtype != torch.float64 or not t.is_contiguous() or t.dim() != 2 or t.shape[0] != P
+            or t.shape[1] != length or not t.is_cuda):
+        raise ValueError("%s must be a contiguous float64 GPU tensor of shape (%d, %d)" % (name, P, length))
+
+
+def max_rows(p: int) -> int:
+    return lib().mdls_max_rows(p)
+
+
+def workspace_bytes(p: int, m: int, n: int, tile: int) -> int:
+    return lib().mdls_workspace_bytes(p, m, n, tile)
+
+
+def workspace(p: int, m: int, n: int, tile: int, device="cuda"):
+    import torch
+
+    nb = workspace_bytes(p, m, n, tile)
+    if nb == 0:
+        raise ValueError("invalid sizes for a workspace")
+    return torch.empty(nb, dtype=torch.uint8, device=device)
+
+
+def qr(p: int, A, tile: int, T=None, ws=None):
+    """In-place QR of A (P, n, m); T (P, n, ldt) or None receives the tile T factors."""
+    m, n = _mat(A, p, "A")
+    if ws is None:
+        ws = workspace(p, m, n, tile, A.device)
+    ldt = 0
+    if T is not None:
+        ldt, _ = _mat(T, p, "T")
+    rc = lib().mdls_qr(p, m, n, tile, _ptr(A), m, _ptr(T), ldt, _ptr(ws), ws.numel(), _stream())
+    _check(rc, "mdls_qr")
+    return A, T
+
+
+def apply_qt(p: int, A, T, B, tile: int, ws=None):
+    """B (P, nrhs, m) := Q^T B, in place."""
+    m, n = _mat(A, p, "A")
+    ldt, _ = _mat(T, p, "T")
+    ldb, nrhs = _mat(B, p, "B")
+    if ws is None:
+        ws = workspace(p, m, n, tile, A.device)
+    rc = lib().mdls_apply_qt(p, m, n, tile, _ptr(A), m, _ptr(T), ldt, _ptr(B), ldb, nrhs, _ptr(ws),
+                             ws.numel(), _stream())
+    _check(rc, "mdls_apply_qt")
+    return B
+
+
+def form_w(p: int, A, T, tile: int, W):
+    """W (P, n, m) := the paper's W factors, W_k = -Y_k T_k."""
+    m, n = _mat(A, p, "A")
+    ldt, _ = _mat(T, p, "T")
+    ldw, _ = _mat(W, p, "W")
+    rc = lib().mdls_form_w(p, m, n, tile, _ptr(A), m, _ptr(T), ldt, _ptr(W), ldw, _stream())
+    _check(rc, "mdls_form_w")
+    return W
+
+
+def backsub(p: int, R, x, tile: int, n: int | None = None, ws=None, info=None):
+    """Solve R(0:n,0:n) x = y; x (P, n) holds y on entry.  Returns (x, info tensor)."""
+    import torch
+
+    ldr, cols = _mat(R, p, "R")
+    if n is None:
+        n = cols
+    _vec(x, p, "x", n)
+    if ws is None:
+        ws = workspace(p, n, n, tile, R.device)
+    if info is None:
+        info = torch.zeros(1, dtype=torch.int32, device=R.device)
+    rc = lib().mdls_backsub(p, n, tile, _ptr(R), ldr, _ptr(x), _ptr(ws), ws.numel(), _ptr(info), _stream())
+    _check(rc, "mdls_backsub")
+    return x, info
+
+
+def solve(p: int, A, b, tile: int, x=None, ws=None, info=None):
+    """Least squares: A (P, n, m) and b (P, m) are overwritten; returns (x, info)."""
+    import torch
+
+    m, n = _mat(A, p, "A")
+    _vec(b, p, "b", m)
+    if x is None:
+        x = torch.empty((p, n), dtype=torch.float64, device=A.device)
+    _vec(x, p, "x", n)
+    if ws is None:
+        ws = workspace(p, m, n, tile, A.device)
+    if info is None:
+        info = torch.zeros(1, dtype=torch.int32, device=A.device)
+    rc = lib().mdls_solve(p, m, n, tile, _ptr(A), m, _ptr(b), _ptr(x), _ptr(ws), ws.numel(), _ptr(info),
+                          _stream())
+    _check(rc, "mdls_solve")
+    return x, info
+
+
+def timing_enable(on: bool = True):
+    lib().mdls_timing_enable(1 if on else 0)
+
+
+def timing_reset():
+    lib().mdls_timing_reset()
+
+
+def timing_kernels():
+    buf = ctypes.create_string_buffer(4096)
+    lib().mdls_timing_kernels(buf, 4096)
+    return [n for n in buf.value.decode().split("\n") if n]
+
+
+def timing_query(name: str = "", p: int = 0):
+    """(total milliseconds, launches, algorithmic md multiply-adds) of the recorded launches."""
+    ms = ctypes.c_double(0)
+    cnt = ctypes.c_long(0)
+    work = ctypes.c_double(0)
+    _check(lib().mdls_timing_query(name.encode(), p, ctypes.byref(ms), ctypes.byref(cnt), ctypes.byref(work)),
+           "mdls_timing_query")
+    return ms.value, cnt.value, work.value

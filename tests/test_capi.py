@@ -1,0 +1,91 @@
+"""The C ABI library loads and exports every entry point include/mdls.h declares, and
+rejects invalid arguments on the host before anything is enqueued (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2110_08375_amd import build, mdls
+
+    if not os.path.exists(mdls._LIB_PATH):
+        build.build_library()
+    return mdls.lib()
+
+
+def declared_functions():
+    txt = open(os.path.join(ROOT, "include", "mdls.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(mdls_[a-z_]+)\s*\(", txt)))
+
+
+def test_exports_every_declared_symbol(L):
+    names = declared_functions()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(L, n), n
+    from paper_2110_08375_amd import mdls
+
+    assert sorted(mdls.EXPORTS) == names
+
+
+def test_workspace_and_limits(L):
+    assert L.mdls_workspace_bytes(2, 1024, 1024, 128) > 0
+    assert L.mdls_workspace_bytes(3, 1024, 1024, 128) == 0  # P not in {1,2,4,8}
+    assert L.mdls_workspace_bytes(2, 10, 20, 4) == 0  # m < n
+    assert L.mdls_workspace_bytes(2, 10, 10, 0) == 0
+    for p in (1, 2, 4, 8):
+        assert L.mdls_max_rows(p) >= 2048
+    assert L.mdls_max_rows(5) == 0
+
+
+def test_solve_argument_errors(L):
+    vp = ctypes.c_void_p
+    dummy = vp(16)  # never dereferenced: validation fails first
+    ws = L.mdls_workspace_bytes(2, 64, 32, 16)
+    s = L.mdls_solve
+    assert s(3, 64, 32, 16, dummy, 64, dummy, dummy, dummy, ws, dummy, None) == -1
+    assert s(2, 0, 32, 16, dummy, 64, dummy, dummy, dummy, ws, dummy, None) == -2
+    assert s(2, 16, 32, 16, dummy, 64, dummy, dummy, dummy, ws, dummy, None) == -3
+    assert s(2, 64, 32, 12, dummy, 64, dummy, dummy, dummy, ws, dummy, None) == -4  # n % tile
+    assert s(2, 64, 32, 16, None, 64, dummy, dummy, dummy, ws, dummy, None) == -5
+    assert s(2, 64, 32, 16, dummy, 63, dummy, dummy, dummy, ws, dummy, None) == -6
+    assert s(2, 64, 32, 16, dummy, 64, None, dummy, dummy, ws, dummy, None) == -7
+    assert s(2, 64, 32, 16, dummy, 64, dummy, None, dummy, ws, dummy, None) == -8
+    assert s(2, 64, 32, 16, dummy, 64, dummy, dummy, None, ws, dummy, None) == -9
+    assert s(2, 64, 32, 16, dummy, 64, dummy, dummy, dummy, ws - 1, dummy, None) == -10
+    assert s(2, 64, 32, 16, dummy, 64, dummy, dummy, dummy, ws, None, None) == -11
+    big = L.mdls_max_rows(2) + 1
+    wsb = L.mdls_workspace_bytes(2, big, 32, 16)
+    assert s(2, big, 32, 16, dummy, big, dummy, dummy, dummy, wsb, dummy, None) == -101
+
+
+def test_other_entry_point_errors(L):
+    vp = ctypes.c_void_p
+    d = vp(16)
+    ws = L.mdls_workspace_bytes(4, 64, 32, 16)
+    assert L.mdls_qr(4, 64, 32, 12, d, 64, d, 12, d, ws, None) == -4  # T wants n % tile == 0
+    assert L.mdls_qr(4, 64, 32, 16, d, 64, d, 8, d, ws, None) == -8  # ldt < tile
+    assert L.mdls_backsub(4, 30, 16, d, 30, d, d, ws, d, None) == -3
+    assert L.mdls_backsub(4, 32, 16, d, 31, d, d, ws, d, None) == -5
+    assert L.mdls_backsub(4, 32, 16, d, 32, d, d, ws, None, None) == -9
+    assert L.mdls_apply_qt(4, 64, 32, 16, d, 64, None, 16, d, 64, 1, d, ws, None) == -7
+    assert L.mdls_apply_qt(4, 64, 32, 16, d, 64, d, 16, d, 64, -1, d, ws, None) == -11
+    assert L.mdls_form_w(4, 64, 32, 16, d, 64, d, 16, d, 63, None) == -10
+    assert L.mdls_status_string(0) == b"success"
+    assert b"invalid" in L.mdls_status_string(-3)
+
+
+def test_binding_refuses_cpu_tensors(L):
+    torch = pytest.importorskip("torch")
+    import paper_2110_08375_amd as M
+
+    A = torch.zeros((2, 4, 8), dtype=torch.float64)
+    b = torch.zeros((2, 8), dtype=torch.float64)
+    with pytest.raises(ValueError):
+        M.solve(2, A, b, 4)
