@@ -173,11 +173,11 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        sample = [(2, 384), (4, 192), (8, 96)]
+        sample = [(2, 1024), (4, 512), (8, 256)]
         v, secs = cpu_baseline(sample, threads)
         cpu = {"value": v, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
                "sample": "oracle least squares (unblocked Householder QR + Q^T b + back substitution) on square "
-                         "dd n=384, qd n=192, od n=96 with the same input recipe; %.1f s" % secs}
+                         "dd n=1024, qd n=512, od n=256 with the same input recipe; %.1f s" % secs}
 
     out = {
         "metric": METRIC,

@@ -17,6 +17,10 @@ from .mdls import (  # noqa: F401
     qr,
     solve,
     status_string,
+    timing_enable,
+    timing_kernels,
+    timing_query,
+    timing_reset,
     workspace,
     workspace_bytes,
 )
