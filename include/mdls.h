@@ -12,8 +12,13 @@
  * of doubles, most significant limb first.  Plane k starts ld * cols doubles after plane
  * k - 1 and is column-major with leading dimension ld >= rows.  A vector of length L is P
  * planes of L doubles.  Every pointer below is a DEVICE pointer.  The caller owns every
- * buffer; the library never allocates, frees or synchronises, and enqueues all work on the
- * caller's stream, so a call sequence can be captured into a HIP graph.
+ * buffer; the library never allocates device memory, frees or synchronises.  Work is enqueued
+ * on the caller's stream; the QR additionally forks part of each trailing update onto a
+ * side stream owned by the calling host thread (created once per device on first use, default
+ * priority) and joins it back with events before returning, so the caller's stream orders
+ * everything and a call sequence can still be captured into a HIP graph (the first call on a
+ * thread should happen outside capture).  MDLS_LOOKAHEAD=0 keeps all work on the caller's
+ * stream.
  *
  * Errors: a call returns 0 on success; -i when argument i (1-based) is invalid, checked on
  * the host before anything is enqueued (LAPACK convention); MDLS_EHIP when a launch fails.

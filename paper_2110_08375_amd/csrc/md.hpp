@@ -12,9 +12,9 @@
 // level is summed with a TwoSum chain whose errors move down one level, and the last level
 // is summed with plain additions and FMAs.  The P level sums form a lazy accumulator that
 // a dot product keeps across many terms; one renormalisation (two bottom-up VecSum passes
-// and a top-down TwoSum pass) turns it back into P limbs.  Reciprocal and reciprocal square
-// root use Newton iterations that double the number of limbs at each step (one step per
-// doubling), so their cost is dominated by the last, full-precision step.
+// and a top-down TwoSum pass) turns it back into P limbs.  Reciprocal, square root and
+// reciprocal square root use Newton steps that double the number of limbs (1 -> 2 -> 4 -> 8),
+// each with its residual formed to full length and its correction to half length.
 //
 // Accuracy contract (normwise): for add/fma the error is a small multiple of
 // 2^(-53P) * (|c| + |a*b|); for mul, recip, div and sqrt it is a small multiple of
@@ -152,6 +152,20 @@ MDQ V<P> renorm(double (&x)[N])
 #pragma unroll
         for (int i = P; i < N; ++i) eps += x[i];
         r.x[P - 1] = eps;
+        // Exact cancellation at the top leaves zero limbs between nonzero ones (e.g.
+        // [s, 0, e, 0]); move them to the end (odd-even transposition, branch-free) so that
+        // limb 0 always leads and truncation keeps the significant limbs.
+#pragma unroll
+        for (int pass = 0; pass < P; ++pass) {
+#pragma unroll
+            for (int i = pass & 1; i + 1 < P; i += 2) {
+                const bool z = (r.x[i] == 0.0);
+                const double hi = z ? r.x[i + 1] : r.x[i];
+                const double lo = z ? 0.0 : r.x[i + 1];
+                r.x[i] = hi;
+                r.x[i + 1] = lo;
+            }
+        }
     }
     return r;
 }
@@ -162,6 +176,18 @@ MDQ V<P> acc_get(const Acc<P> &a)
     double t[P];
 #pragma unroll
     for (int k = 0; k < P; ++k) t[k] = a.s[k];
+    return renorm<P, P>(t);
+}
+
+// Renormalise twice: merges the overlapping limbs a first pass can leave after cancellation
+// (e.g. [e, -4e', e', 0] with e' ~ ulp(e)); used where a value is truncated afterwards.
+template <int P>
+MDQ V<P> acc_get_strict(const Acc<P> &a)
+{
+    const V<P> v = acc_get(a);
+    double t[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) t[k] = v.x[k];
     return renorm<P, P>(t);
 }
 
@@ -184,52 +210,49 @@ MDQ Acc<P> acc_zero()
 }
 
 // ------------------------------------------------------------------ level cascades
-// s += a*b.  HAS_S = false means s is zero on entry (plain product).
-template <int P, int L, int NC, bool HAS_S>
-MDQ void casc_fma(double (&s)[P], const double (&a)[P], const double (&b)[P], const double *carry)
+// s += a*b with a of NA limbs and b of NB limbs (NA, NB <= P); only the products
+// a_i b_j with i + j <= P - 1 are formed, as TwoProd pairs up to level P - 2 and as plain
+// FMAs at level P - 1.  HAS_S = false means s is zero on entry (a plain product).  Level L
+// sums, in this order, s_L, the products of level L and the NC terms carried from level
+// L - 1 with a TwoSum chain; the chain's rounding errors and the TwoProd errors of level L
+// are carried to level L + 1.
+template <int P, int NA, int NB, int L, int NC, bool HAS_S>
+MDQ void casc_fma(double (&s)[P], const double *a, const double *b, const double *carry)
 {
+    constexpr int ILO = (L - NB + 1 > 0) ? (L - NB + 1) : 0;
+    constexpr int IHI = (L < NA - 1) ? L : (NA - 1);
+    constexpr int NP = (IHI >= ILO) ? (IHI - ILO + 1) : 0;
     if constexpr (L == P - 1) {
         double t;
-        if constexpr (HAS_S) {
+        if constexpr (HAS_S)
             t = s[L];
+        else if constexpr (NC > 0)
+            t = carry[0];
+        else
+            t = 0.0;
+        constexpr int K0 = (!HAS_S && NC > 0) ? 1 : 0;
 #pragma unroll
-            for (int k = 0; k < NC; ++k) t += carry[k];
-        } else {
-            t = (NC > 0) ? carry[0] : 0.0;
+        for (int k = K0; k < NC; ++k) t += carry[k];
 #pragma unroll
-            for (int k = 1; k < NC; ++k) t += carry[k];
-        }
-#pragma unroll
-        for (int i = 0; i <= L; ++i) t = __builtin_fma(a[i], b[L - i], t);
+        for (int i = ILO; i <= IHI; ++i) t = __builtin_fma(a[i], b[L - i], t);
         s[L] = t;
     } else {
-        constexpr int NP = L + 1;
-        constexpr int NOUT = NC + 2 * NP - (HAS_S ? 0 : 1);
-        double out[NOUT];
-        double t;
-        int o = 0;
-        double pe0;
-        two_prod(a[0], b[L], t, pe0);
-        if constexpr (HAS_S) {
-            two_sum(s[L], t, t, out[o]);
-            ++o;
-        }
-        out[o++] = pe0;
+        constexpr int NT = (HAS_S ? 1 : 0) + NP + NC;
+        constexpr int NSE = (NT > 0) ? NT - 1 : 0;  // TwoSum errors
+        constexpr int NOUT = NSE + NP;
+        double out[NOUT > 0 ? NOUT : 1];
+        double tm[NT > 0 ? NT : 1];
+        constexpr int Q0 = HAS_S ? 1 : 0;
+        if constexpr (HAS_S) tm[0] = s[L];
 #pragma unroll
-        for (int i = 1; i <= L; ++i) {
-            double p, pe;
-            two_prod(a[i], b[L - i], p, pe);
-            two_sum(t, p, t, out[o]);
-            ++o;
-            out[o++] = pe;
-        }
+        for (int i = ILO; i <= IHI; ++i) two_prod(a[i], b[L - i], tm[Q0 + i - ILO], out[NSE + i - ILO]);
 #pragma unroll
-        for (int k = 0; k < NC; ++k) {
-            two_sum(t, carry[k], t, out[o]);
-            ++o;
-        }
+        for (int k = 0; k < NC; ++k) tm[Q0 + NP + k] = carry[k];
+        double t = (NT > 0) ? tm[0] : 0.0;
+#pragma unroll
+        for (int k = 1; k < NT; ++k) two_sum(t, tm[k], t, out[k - 1]);
         s[L] = t;
-        casc_fma<P, L + 1, NOUT, HAS_S>(s, a, b, out);
+        casc_fma<P, NA, NB, L + 1, NOUT, HAS_S>(s, a, b, out);
     }
 }
 
@@ -254,32 +277,10 @@ MDQ void casc_add(double (&s)[P], const double (&b)[P], const double *carry)
     }
 }
 
-// s += q*b with q a double
-template <int P, int L, int NC>
-MDQ void casc_fma_d(double (&s)[P], double q, const double (&b)[P], const double *carry)
-{
-    if constexpr (L == P - 1) {
-        double t = s[L];
-#pragma unroll
-        for (int k = 0; k < NC; ++k) t += carry[k];
-        s[L] = __builtin_fma(q, b[L], t);
-    } else {
-        constexpr int NOUT = NC + 2;
-        double out[NOUT];
-        double t, p;
-        two_prod(q, b[L], p, out[0]);
-        two_sum(s[L], p, t, out[1]);
-#pragma unroll
-        for (int k = 0; k < NC; ++k) two_sum(t, carry[k], t, out[k + 2]);
-        s[L] = t;
-        casc_fma_d<P, L + 1, NOUT>(s, q, b, out);
-    }
-}
-
 template <int P>
 MDQ void acc_fma(Acc<P> &acc, const V<P> &a, const V<P> &b)
 {
-    casc_fma<P, 0, 0, true>(acc.s, a.x, b.x, nullptr);
+    casc_fma<P, P, P, 0, 0, true>(acc.s, a.x, b.x, nullptr);
 }
 
 template <int P>
@@ -291,7 +292,7 @@ MDQ void acc_add(Acc<P> &acc, const V<P> &b)
 template <int P>
 MDQ void acc_fma_d(Acc<P> &acc, double q, const V<P> &b)
 {
-    casc_fma_d<P, 0, 0>(acc.s, q, b.x, nullptr);
+    casc_fma<P, 1, P, 0, 0, true>(acc.s, &q, b.x, nullptr);
 }
 
 // Long accumulations renormalise the level sums every kLazy<P> terms: left alone, the lower
@@ -328,7 +329,7 @@ template <int P>
 MDQ V<P> mul(const V<P> &a, const V<P> &b)
 {
     Acc<P> t;
-    casc_fma<P, 0, 0, false>(t.s, a.x, b.x, nullptr);
+    casc_fma<P, P, P, 0, 0, false>(t.s, a.x, b.x, nullptr);
     return acc_get(t);
 }
 
@@ -350,7 +351,23 @@ MDQ V<P> mul_d(const V<P> &a, double q)
     return acc_get(t);
 }
 
-// 1/b: Newton y <- y + y (1 - b y), one step per doubling of the limb count.
+// Concatenate a P/2-limb value and a P/2-limb correction lying just below it, renormalise.
+template <int P>
+MDQ V<P> join_halves(const V<P / 2> &hi, const V<P / 2> &lo)
+{
+    double t[P];
+#pragma unroll
+    for (int k = 0; k < P / 2; ++k) {
+        t[k] = hi.x[k];
+        t[P / 2 + k] = lo.x[k];
+    }
+    return renorm<P, P>(t);
+}
+
+// 1/b.  Limb-doubling Newton step (Karp and Markstein, "High-precision division and square
+// root", ACM TOMS 1997): with y ~ 1/b to P/2 limbs, the residual e = 1 - b y is formed to P
+// limbs (it is about 2^(-26P) relative, so only its top P/2 limbs matter) and the correction
+// y e is a P/2-limb product: y + y e is 1/b to P limbs.
 template <int P>
 MDQ V<P> recip(const V<P> &b)
 {
@@ -359,11 +376,13 @@ MDQ V<P> recip(const V<P> &b)
         r.x[0] = 1.0 / b.x[0];
         return r;
     } else {
-        V<P> y = resize<P>(recip<P / 2>(resize<P / 2>(b)));
+        constexpr int H = P / 2;
+        const V<H> y = recip<H>(resize<H>(b));
         Acc<P> e = acc_from(from_double<P>(1.0));
-        acc_fma(e, neg(b), y);
-        V<P> ev = acc_get(e);  // 1 - b y, about 2^(-26P) relative
-        return fma(y, y, ev);
+        const V<P> nb = neg(b);
+        casc_fma<P, P, H, 0, 0, true>(e.s, nb.x, y.x, nullptr);
+        const V<H> eh = resize<H>(acc_get_strict(e));
+        return join_halves<P>(y, mul(y, eh));
     }
 }
 
@@ -373,7 +392,8 @@ MDQ V<P> div(const V<P> &a, const V<P> &b)
     return mul(a, recip(b));
 }
 
-// 1/sqrt(a), a > 0: Newton y <- y + y (1 - a y^2) / 2, one step per doubling.
+// 1/sqrt(a), a > 0: y + y (1 - a y^2) / 2 with y to P/2 limbs, the residual to P limbs and
+// the correction as a P/2-limb product.
 template <int P>
 MDQ V<P> rsqrt(const V<P> &a)
 {
@@ -382,16 +402,22 @@ MDQ V<P> rsqrt(const V<P> &a)
         r.x[0] = 1.0 / sqrt(a.x[0]);
         return r;
     } else {
-        V<P> y = resize<P>(rsqrt<P / 2>(resize<P / 2>(a)));
-        V<P> y2 = mul(y, y);
+        constexpr int H = P / 2;
+        const V<H> y = rsqrt<H>(resize<H>(a));
+        Acc<P> y2a;
+        casc_fma<P, H, H, 0, 0, false>(y2a.s, y.x, y.x, nullptr);
+        const V<P> y2 = acc_get_strict(y2a);  // y^2 to P limbs
         Acc<P> e = acc_from(from_double<P>(1.0));
-        acc_fma(e, neg(a), y2);
-        V<P> ev = scale(acc_get(e), 0.5);
-        return fma(y, y, ev);
+        const V<P> na = neg(a);
+        casc_fma<P, P, P, 0, 0, true>(e.s, na.x, y2.x, nullptr);
+        const V<H> eh = scale(resize<H>(acc_get_strict(e)), 0.5);
+        return join_halves<P>(y, mul(y, eh));
     }
 }
 
-// sqrt(a), a >= 0 (zero maps to zero)
+// sqrt(a), a >= 0 (zero maps to zero).  Karp-Markstein: s = a y to P/2 limbs with
+// y = 1/sqrt(a) to P/2 limbs, the residual a - s^2 to P limbs, and the correction
+// (a - s^2) y / 2 as a P/2-limb product.
 template <int P>
 MDQ V<P> sqrt_md(const V<P> &a)
 {
@@ -401,7 +427,15 @@ MDQ V<P> sqrt_md(const V<P> &a)
         r.x[0] = sqrt(a.x[0]);
         return r;
     } else {
-        return mul(a, rsqrt(a));
+        constexpr int H = P / 2;
+        const V<H> ah = resize<H>(a);
+        const V<H> y = rsqrt<H>(ah);
+        const V<H> sh = mul(ah, y);
+        Acc<P> r = acc_from(a);
+        const V<H> nsh = neg(sh);
+        casc_fma<P, H, H, 0, 0, true>(r.s, nsh.x, sh.x, nullptr);
+        const V<H> rh = resize<H>(acc_get_strict(r));
+        return join_halves<P>(sh, mul(rh, scale(y, 0.5)));
     }
 }
 

@@ -45,6 +45,45 @@ hipEvent_t pool_get()
 namespace mdls_impl {
 bool timing_on() { return g_on; }
 
+SideStream *side_stream()
+{
+    struct PerThread {
+        int dev = -1;
+        SideStream ss{};
+        bool ok = false;
+    };
+    static thread_local PerThread slots[16];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 16) return nullptr;
+    PerThread &p = slots[dev];
+    if (!p.ok) {
+        if (hipStreamCreateWithFlags(&p.ss.q, hipStreamNonBlocking) != hipSuccess) return nullptr;
+        if (hipEventCreateWithFlags(&p.ss.ev_panel, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&p.ss.ev_wide[0], hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&p.ss.ev_wide[1], hipEventDisableTiming) != hipSuccess)
+            return nullptr;
+        p.dev = dev;
+        p.ok = true;
+    }
+    return &p.ss;
+}
+
+bool lookahead_on()
+{
+    const char *e = getenv("MDLS_LOOKAHEAD");
+    return !(e && e[0] == '0');
+}
+
+int apply_grid_cap()
+{
+    const char *e = getenv("MDLS_APPLY_GRID_CAP");
+    if (e) {
+        const int v = atoi(e);
+        if (v > 0) return v;
+    }
+    return 224;
+}
+
 void timing_begin(hipStream_t s, void **ev)
 {
     std::lock_guard<std::mutex> lk(g_mu);
@@ -110,7 +149,8 @@ extern "C" {
 int mdls_max_rows(int p)
 {
     if (!valid_p(p)) return 0;
-    return kGMax * kThreads * panel_rows_per_thread(p);
+    const PanelCfg cf = panel_cfg(p);
+    return kGMax * (cf.nt / leaf_width(p)) * cf.r;
 }
 
 size_t mdls_workspace_bytes(int p, int m, int n, int tile)

@@ -22,6 +22,7 @@
 // arithmetic.
 #include <climits>
 #include <cstdint>
+#include <cstdio>
 #include <cstdlib>
 
 #pragma once
@@ -33,18 +34,31 @@ using namespace mdk;
 
 // ============================================================================ panel kernel
 struct PanelArgs {
-    double *A;  // top-left (diagonal) element of the panel
+    double *A;  // panel column 0 at row (diagonal - off); the panel's diagonal is row off
     long lda, ps;
-    int h, wact;   // panel rows (from the diagonal down), active columns (<= W)
+    int h, wact;   // rows from the diagonal down, active columns (<= W)
+    int off;       // W when the previous panel is applied first (rows above the diagonal), else 0
+    const double *Yp;  // previous panel's diagonal element (its Y, unit lower trapezoidal), if off
+    const double *Tp;  // previous panel's T (W x W, ld W), plane stride tps
     double *beta;  // beta of the panel's first column, plane stride bps
     long bps;
     double *T;  // panel T, W x W column-major (ld W), plane stride tps
     long tps;
-    double *gpart;  // [2][G][2W][P] exchange slots between workgroups
+    double *gpart;  // [2][G][W*W + 2W][P] exchange slots between workgroups
     unsigned *gbar; // barrier counter of this launch, zero on entry
     int *err;       // set to 1 if a barrier times out
     int G;          // workgroups in the launch
 };
+
+// Entry (r, c) of a block of Householder vectors stored below the diagonal of A: zero above
+// the diagonal, the implicit one on it, the stored value below; zero outside h x wact.
+template <int P>
+__device__ __forceinline__ V<P> y_entry(const double *Y, long ldy, long psy, long r, int c, int h, int wact)
+{
+    if (r >= h || c >= wact || r < c) return zero<P>();
+    if (r == c) return from_double<P>(1.0);
+    return ldm<P>(Y, psy, (long)c * ldy + r);
+}
 
 // All workgroups of the launch meet here (called by one whole wave per workgroup).  The
 // spin is bounded: a timed-out barrier raises *err and lets the wave continue, so the grid
@@ -58,7 +72,7 @@ __device__ inline void grid_sync(unsigned *ctr, unsigned target, int *err)
         unsigned spins = 0;
         while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
             __builtin_amdgcn_s_sleep(1);
-            if (++spins > (1u << 20)) {
+            if (++spins > (1u << 22)) {
                 __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 break;
             }
@@ -67,165 +81,320 @@ __device__ inline void grid_sync(unsigned *ctr, unsigned target, int *err)
     __threadfence();
 }
 
-template <int P, int W, int R>
-__global__ __launch_bounds__(kThreads) void k_panel(PanelArgs g)
+// Thread (slot, c) of workgroup b holds column c of rows b*S + slot + k*G*S, k < R, where
+// S = NT/W row slots per workgroup: the W threads of a row are consecutive lanes.  Rows are
+// counted from `off` rows above the panel's diagonal.
+//
+// When off = W the kernel first applies the previous panel's block reflector to its own
+// columns, C := C - Y' T'^T (Y'^T C) over the rows from the previous diagonal down (this is
+// the look-ahead: the rest of the trailing matrix is updated by k_apply concurrently).
+//
+// Column j of the panel, x = A(j:h, j) with x1 = a_jj, sigma = sum_{i>j} x_i^2, mu = ||x||:
+// the Householder vector is kept unnormalised as u = gamma (x - mu e1), with
+//   x1 <= 0: gamma = 1,        u1 = x1 - mu, tau = -1/(mu u1),
+//   x1 >  0: gamma = x1 + mu,  u1 = -sigma,  tau = 1/(mu sigma gamma),
+// (both without cancellation, Golub-Van Loan 5.1.1), so that H = I - tau u u^T and the
+// per-column chain needs one reciprocal.  For c > j, with d_c = sum_{i>j} x_i a_ic from the
+// same reduction as sigma, s_c = tau (u1 a_jc + gamma d_c) and the update is a_ic -= s_c
+// gamma x_i (i > j), a_jc -= s_c u1.  At the end of the panel v = u / u1 (scale rho =
+// gamma/u1 on the stored x), beta = tau u1^2 and T are formed.
+template <int P, int W, int R, int NT>
+__global__ __launch_bounds__(NT) void k_panel(PanelArgs g)
 {
-    __shared__ double s_wred[4][W][P];
-    __shared__ double s_head[W][P];
-    __shared__ double s_bw[W][P];
-    __shared__ double s_sc[2][P];  // rv = 1/v1, mu
-    __shared__ int s_flag;
+    constexpr int S = NT / W;
+    constexpr int NW = NT / 64;
+    constexpr int SLOT = (W * W + 2 * W) * P;  // doubles per workgroup exchange slot
+    static_assert(64 % W == 0 && S >= 2 * W, "panel layout");
+    __shared__ double s_part[NW * W * W * P];
+    __shared__ double s_head[W * P];
+    __shared__ double s_coef[W * P];
+    __shared__ double s_rowj[W * P];
+    __shared__ double s_mu[P];
+    __shared__ double s_info[W * 3 * P];  // per column: u1, gamma, tau
+    __shared__ double s_gram[W * W * P];  // [j][l]: sum_{i>j} x_j(i) x_l(i), l < j; then g(l, j)
+    __shared__ double s_hrow[W * W * P];  // [j][l]: a_jl when column j is processed
+    __shared__ double s_rho[W * P];
+    __shared__ int s_flag[W];             // sigma == 0
 
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const long stride = (long)g.G * kThreads;
-    const long gt = (long)blockIdx.x * kThreads + tid;
+    const int c = tid % W, slot = tid / W;
+    const long rstride = (long)g.G * S;
+    const long rbase = (long)blockIdx.x * S + slot;
+    const int src0 = lane & ~(W - 1);
+    const int off = g.off;
+    const long hh = (long)g.h + off;
+    unsigned nbar = 0;
 
-    V<P> a[R][W];
+    V<P> a[R];
 #pragma unroll
     for (int k = 0; k < R; ++k) {
-        const long r = gt + k * stride;
-#pragma unroll
-        for (int c = 0; c < W; ++c)
-            a[k][c] = (r < g.h && c < g.wact) ? ldm<P>(g.A, g.ps, c * g.lda + r) : zero<P>();
+        const long r = rbase + k * rstride;
+        a[k] = (r < hh && c < g.wact) ? ldm<P>(g.A, g.ps, c * g.lda + r) : zero<P>();
     }
-    V<P> trow[W];  // row `lane` of T, kept by wave 0 of workgroup 0
-#pragma unroll
-    for (int c = 0; c < W; ++c) trow[c] = zero<P>();
 
+    // ---- 0. apply the previous panel's reflectors to this panel (look-ahead update)
+    if (off) {
+        Acc<P> sacc[W];
 #pragma unroll
-    for (int j = 0; j < W; ++j) {
-        if (j >= g.wact) break;
-        // ---- 1. one reduction per column: sigma = sum_{i>j} a_ij^2, d_c = sum_{i>j} a_ij a_ic
-        //         (c > j) and the Gram entries sum_{i>j} a_ij y_il (l < j) for T.
+        for (int i = 0; i < W; ++i) sacc[i] = acc_zero<P>();
 #pragma unroll
-        for (int q = 0; q < W; ++q) {
-            const int col = (q == 0) ? j : (q <= j ? q - 1 : q);
-            Acc<P> acc = acc_zero<P>();
+        for (int k = 0; k < R; ++k) {
+            const long r = rbase + k * rstride;
+            if (r < hh) {
 #pragma unroll
-            for (int k = 0; k < R; ++k) {
-                const long r = gt + k * stride;
-                if (r > j && r < g.h) acc_fma(acc, a[k][j], a[k][col]);
+                for (int i = 0; i < W; ++i)
+                    acc_fma_step(sacc[i], y_entry<P>(g.Yp, g.lda, g.ps, r, i, (int)hh, W), a[k], k);
             }
-            const V<P> s = wave_sum(acc_get(acc));
-            if (lane == 0) lds_st(s_wred[wid][q], s);
         }
-        if (blockIdx.x == 0 && tid == j) {
 #pragma unroll
-            for (int c = 0; c < W; ++c) lds_st(s_head[c], a[0][c]);
+        for (int i = 0; i < W; ++i) {
+#pragma unroll
+            for (int m = W; m < 64; m <<= 1) acc_add_acc(sacc[i], shfl_xor_acc(sacc[i], m));
+            if (lane < W) {
+#pragma unroll
+                for (int k = 0; k < P; ++k) s_part[((wid * W + i) * W + lane) * P + k] = sacc[i].s[k];
+            }
         }
         __syncthreads();
         if (wid == 0) {
-            // lane q < W holds total q and head-row entry q
-            V<P> tot = zero<P>(), hd = zero<P>();
-            if (lane < W) {
-                tot = lds_ld<P>(s_wred[0][lane]);
+            // pairs (i, cc) = (q / W, q % W) for q = lane, lane + 64, ...
+            for (int q = lane; q < W * W; q += 64) {
+                Acc<P> t = acc_zero<P>();
+                for (int w = 0; w < NW; ++w) {
+                    Acc<P> o;
 #pragma unroll
-                for (int w = 1; w < 4; ++w) tot = add(tot, lds_ld<P>(s_wred[w][lane]));
-                if (blockIdx.x == 0) hd = lds_ld<P>(s_head[lane]);
+                    for (int k = 0; k < P; ++k) o.s[k] = s_part[(w * W * W + q) * P + k];
+                    acc_add_acc(t, o);
+                }
+                if (g.G > 1) {
+                    double *mine = g.gpart + (size_t)((nbar & 1) * g.G + blockIdx.x) * SLOT;
+#pragma unroll
+                    for (int k = 0; k < P; ++k) st_coherent(mine + q * P + k, t.s[k]);
+                } else {
+                    lds_st(&s_gram[q * P], acc_get(t));
+                }
             }
             if (g.G > 1) {
-                double *slot = g.gpart + (size_t)((j & 1) * g.G + blockIdx.x) * (2 * W * P);
-                if (lane < W) {
+                grid_sync(g.gbar, (nbar + 1) * (unsigned)g.G, g.err);
+                const double *base = g.gpart + (size_t)((nbar & 1) * g.G) * SLOT;
+                for (int q = lane; q < W * W; q += 64) {
+                    Acc<P> t = acc_zero<P>();
+                    for (int b = 0; b < g.G; ++b) {
+                        Acc<P> o;
 #pragma unroll
-                    for (int k = 0; k < P; ++k) st_coherent(slot + lane * P + k, tot.x[k]);
-                    if (blockIdx.x == 0) {
-#pragma unroll
-                        for (int k = 0; k < P; ++k) st_coherent(slot + (W + lane) * P + k, hd.x[k]);
+                        for (int k = 0; k < P; ++k) o.s[k] = ld_coherent(base + (size_t)b * SLOT + q * P + k);
+                        acc_add_acc(t, o);
                     }
-                }
-                grid_sync(g.gbar, (unsigned)(j + 1) * (unsigned)g.G, g.err);
-                if (lane < W) {
-                    const double *base = g.gpart + (size_t)((j & 1) * g.G) * (2 * W * P);
-                    V<P> t2, h2;
-#pragma unroll
-                    for (int k = 0; k < P; ++k) {
-                        t2.x[k] = ld_coherent(base + lane * P + k);
-                        h2.x[k] = ld_coherent(base + (W + lane) * P + k);
-                    }
-                    for (int b = 1; b < g.G; ++b) {
-                        V<P> o;
-#pragma unroll
-                        for (int k = 0; k < P; ++k) o.x[k] = ld_coherent(base + (size_t)b * (2 * W * P) + lane * P + k);
-                        t2 = add(t2, o);
-                    }
-                    tot = t2;
-                    hd = h2;
+                    lds_st(&s_gram[q * P], acc_get(t));
                 }
             }
-            // ---- 2. Householder scalars (identical in every lane and every workgroup)
-            const V<P> sig = shfl_md(tot, 0);
-            const V<P> x1 = shfl_md(hd, j);
-            const bool zsig = is_zero(sig);
-            V<P> mu = x1, beta = zero<P>(), rv = zero<P>();
-            if (!zsig) {
-                mu = sqrt_md(fma(sig, x1, x1));  // ||x||_2
-                V<P> v1;
-                if (x1.x[0] <= 0.0)
-                    v1 = sub(x1, mu);
-                else
-                    v1 = neg(mul(sig, recip(add(x1, mu))));  // -sigma/(x1 + mu), no cancellation
-                const V<P> z = recip(mul(mu, v1));
-                beta = neg(mul(mul(v1, v1), z));  // 2 v1^2/(sigma + v1^2) = -v1/mu
-                rv = mul(mu, z);                  // 1/v1
-            }
-            // ---- 3. per-column values: lane c > j gets beta * (a_jc + d_c / v1)
-            if (lane > j && lane < W) lds_st(s_bw[lane], mul(beta, fma(hd, tot, rv)));
-            // T column j: g_l = y_l^T v_j = y_jl + (sum_{i>j} y_il a_ij) / v1 in lane l < j,
-            // T(l, j) = -beta_j sum_{k=l}^{j-1} T(l, k) g_k, T(j, j) = beta_j
-            const V<P> gs = shfl_md(tot, (lane + 1) & 63);
-            V<P> gl = zero<P>();
-            if (lane < j) gl = fma(hd, gs, rv);
-            Acc<P> tacc = acc_zero<P>();
-#pragma unroll
-            for (int k = 0; k < j; ++k) {
-                const V<P> gk = shfl_md(gl, k);
-                if (lane <= k) acc_fma(tacc, trow[k], gk);
-            }
-            if (lane < j) trow[j] = neg(mul(beta, acc_get(tacc)));
-            if (lane == j) trow[j] = beta;
-            if (lane == 0) {
-                lds_st(s_sc[0], rv);
-                lds_st(s_sc[1], mu);
-                s_flag = zsig ? 1 : 0;
-                if (blockIdx.x == 0) stm(g.beta, g.bps, j, beta);
+        }
+        ++nbar;
+        __syncthreads();
+        // U(i, cc) = sum_{l<=i} T'(l, i) S(l, cc), negated, into s_hrow (scratch)
+        if (wid == 0) {
+            for (int q = lane; q < W * W; q += 64) {
+                const int i = q / W, cc = q % W;
+                Acc<P> u = acc_zero<P>();
+                for (int l = 0; l <= i; ++l)
+                    acc_fma(u, ldm<P>(g.Tp, g.tps, (long)i * W + l), lds_ld<P>(&s_gram[(l * W + cc) * P]));
+                lds_st(&s_hrow[q * P], neg(acc_get(u)));
             }
         }
         __syncthreads();
-        // ---- 4. scale v = x / v1, put mu on the diagonal, apply the reflector to columns > j
-        if (!s_flag) {
-            const V<P> rv = lds_ld<P>(s_sc[0]);
-            const V<P> mu = lds_ld<P>(s_sc[1]);
-            V<P> nbw[W];
 #pragma unroll
-            for (int c = 0; c < W; ++c) nbw[c] = (c > j) ? neg(lds_ld<P>(s_bw[c])) : zero<P>();
+        for (int k = 0; k < R; ++k) {
+            const long r = rbase + k * rstride;
+            if (r < hh && c < g.wact) {
+                Acc<P> t = acc_from(a[k]);
+#pragma unroll
+                for (int i = 0; i < W; ++i)
+                    acc_fma(t, y_entry<P>(g.Yp, g.lda, g.ps, r, i, (int)hh, W), lds_ld<P>(&s_hrow[(i * W + c) * P]));
+                a[k] = acc_get(t);
+            }
+        }
+        __syncthreads();
+    }
+
+    for (int j = 0; j < g.wact; ++j) {
+        const long dj = off + j;  // row of the diagonal element of column j
+        // ---- 1. one reduction per column: thread (slot, c) sums x_j(i) a_c(i) over its rows i > j:
+        //         sigma (c = j), d_c (c > j), the Gram sums for T (c < j)
+        Acc<P> acc = acc_zero<P>();
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const long r = rbase + k * rstride;
+            const V<P> xk = shfl_md(a[k], src0 + j);
+            if (r > dj && r < hh) acc_fma_step(acc, xk, a[k], k);
+        }
+        // the partial sums stay lazy (level sums) through every reduction level below and are
+        // renormalised once, in wave 0
+#pragma unroll
+        for (int m = W; m < 64; m <<= 1) acc_add_acc(acc, shfl_xor_acc(acc, m));
+        if (lane < W) {
+#pragma unroll
+            for (int k = 0; k < P; ++k) s_part[(wid * W + lane) * P + k] = acc.s[k];
+        }
+        if (blockIdx.x == 0 && slot == dj) lds_st(&s_head[c * P], a[0]);
+        __syncthreads();
+        if (wid == 0) {
+            Acc<P> ta = acc_zero<P>();
+            for (int i = lane; i < NW * W; i += 64) {
+                Acc<P> o;
+#pragma unroll
+                for (int k = 0; k < P; ++k) o.s[k] = s_part[i * P + k];
+                acc_add_acc(ta, o);
+            }
+#pragma unroll
+            for (int m = W; m < (NW * W < 64 ? NW * W : 64); m <<= 1) acc_add_acc(ta, shfl_xor_acc(ta, m));
+            V<P> hd = (blockIdx.x == 0) ? lds_ld<P>(&s_head[(lane % W) * P]) : zero<P>();
+            if (g.G > 1) {
+                double *mine = g.gpart + (size_t)((nbar & 1) * g.G + blockIdx.x) * SLOT;
+                if (lane < W) {
+#pragma unroll
+                    for (int k = 0; k < P; ++k) st_coherent(mine + lane * P + k, ta.s[k]);
+                    if (blockIdx.x == 0) {
+#pragma unroll
+                        for (int k = 0; k < P; ++k) st_coherent(mine + (W + lane) * P + k, hd.x[k]);
+                    }
+                }
+                grid_sync(g.gbar, (nbar + 1) * (unsigned)g.G, g.err);
+                const double *base = g.gpart + (size_t)((nbar & 1) * g.G) * SLOT;
+                ta = acc_zero<P>();
+                for (int i = lane; i < g.G * W; i += 64) {
+                    Acc<P> o;
+                    const double *q = base + (size_t)(i / W) * SLOT + (i % W) * P;
+#pragma unroll
+                    for (int k = 0; k < P; ++k) o.s[k] = ld_coherent(q + k);
+                    acc_add_acc(ta, o);
+                }
+                const int lim = (g.G * W < 64) ? g.G * W : 64;
+                for (int m = W; m < lim; m <<= 1) acc_add_acc(ta, shfl_xor_acc(ta, m));
+#pragma unroll
+                for (int k = 0; k < P; ++k) hd.x[k] = ld_coherent(base + (W + lane % W) * P + k);
+            }
+            const V<P> tot = acc_get(ta);
+            // lanes l < W now hold tot = total of column l and hd = a_jl
+            // ---- 2. Householder scalars, identical in every lane and every workgroup
+            const V<P> sig = shfl_md(tot, j);
+            const V<P> x1 = shfl_md(hd, j);
+            const bool zs = is_zero(sig);
+            V<P> mu = x1, u1 = zero<P>(), gam = from_double<P>(1.0), tau = zero<P>();
+            if (!zs) {
+                mu = sqrt_md(fma(sig, x1, x1));
+                if (x1.x[0] <= 0.0) {
+                    u1 = sub(x1, mu);
+                    tau = neg(recip(mul(mu, u1)));
+                } else {
+                    gam = add(x1, mu);
+                    u1 = neg(sig);
+                    tau = recip(mul(mul(mu, sig), gam));
+                }
+            }
+            // ---- 3. per-column multipliers (lane c > j)
+            if (lane > j && lane < W) {
+                const V<P> sc = mul(tau, fma(mul(gam, tot), u1, hd));  // tau (u1 a_jc + gamma d_c)
+                lds_st(&s_coef[lane * P], mul(sc, gam));
+                lds_st(&s_rowj[lane * P], mul(sc, u1));
+            }
+            if (lane < j) {
+                lds_st(&s_gram[(j * W + lane) * P], tot);
+                lds_st(&s_hrow[(j * W + lane) * P], hd);
+            }
+            if (lane == 0) {
+                lds_st(s_mu, mu);
+                lds_st(&s_info[(j * 3 + 0) * P], u1);
+                lds_st(&s_info[(j * 3 + 1) * P], gam);
+                lds_st(&s_info[(j * 3 + 2) * P], tau);
+                s_flag[j] = zs ? 1 : 0;
+            }
+        }
+        ++nbar;
+        __syncthreads();
+        // ---- 4. reflector j applied to the columns c > j; mu on the diagonal
+        if (!s_flag[j]) {
+            const V<P> mu = lds_ld<P>(s_mu);
+            V<P> ncoef = zero<P>(), rowj = zero<P>();
+            if (c > j) {
+                ncoef = neg(lds_ld<P>(&s_coef[c * P]));
+                rowj = lds_ld<P>(&s_rowj[c * P]);
+            }
 #pragma unroll
             for (int k = 0; k < R; ++k) {
-                const long r = gt + k * stride;
-                if (r == j) {
-                    a[k][j] = mu;
-#pragma unroll
-                    for (int c = j + 1; c < W; ++c) a[k][c] = add(a[k][c], nbw[c]);
-                } else if (r > j && r < g.h) {
-                    const V<P> v = mul(a[k][j], rv);
-                    a[k][j] = v;
-#pragma unroll
-                    for (int c = j + 1; c < W; ++c) a[k][c] = fma(a[k][c], nbw[c], v);
+                const long r = rbase + k * rstride;
+                const V<P> xk = shfl_md(a[k], src0 + j);  // column j is unchanged below row j
+                if (r == dj) {
+                    if (c == j)
+                        a[k] = mu;
+                    else if (c > j)
+                        a[k] = sub(a[k], rowj);
+                } else if (r > dj && r < hh && c > j) {
+                    a[k] = fma(a[k], ncoef, xk);
                 }
             }
         }
     }
-#pragma unroll
-    for (int k = 0; k < R; ++k) {
-        const long r = gt + k * stride;
-        if (r < g.h) {
-#pragma unroll
-            for (int c = 0; c < W; ++c)
-                if (c < g.wact) stm(g.A, g.ps, c * g.lda + r, a[k][c]);
+    __syncthreads();
+    // ---- 5. beta, the normalisation rho = gamma/u1 and T, in wave 0
+    if (wid == 0) {
+        V<P> rho = from_double<P>(1.0), beta = zero<P>();
+        if (lane < g.wact && !s_flag[lane]) {
+            const V<P> u1 = lds_ld<P>(&s_info[(lane * 3 + 0) * P]);
+            const V<P> gam = lds_ld<P>(&s_info[(lane * 3 + 1) * P]);
+            const V<P> tau = lds_ld<P>(&s_info[(lane * 3 + 2) * P]);
+            rho = mul(gam, recip(u1));
+            beta = mul(tau, mul(u1, u1));
+        }
+        if (lane < W) {
+            lds_st(&s_rho[lane * P], rho);
+            lds_st(&s_info[(lane * 3 + 0) * P], beta);  // s_info(j, 0) now holds beta_j
+        }
+        if (blockIdx.x == 0 && lane < g.wact) stm(g.beta, g.bps, lane, beta);
+    }
+    __syncthreads();
+    if (wid == 0) {
+        // g(l, j) = y_l^T v_j = rho_l (a_jl + rho_j gsum_jl), l < j, written over s_gram(j, l)
+        for (int q = lane; q < W * W; q += 64) {
+            const int gj = q / W, gl = q % W;
+            if (gl < gj && gj < g.wact) {
+                const V<P> rl = lds_ld<P>(&s_rho[gl * P]), rj = lds_ld<P>(&s_rho[gj * P]);
+                lds_st(&s_gram[q * P],
+                       mul(rl, fma(lds_ld<P>(&s_hrow[q * P]), rj, lds_ld<P>(&s_gram[q * P]))));
+            }
         }
     }
-    if (blockIdx.x == 0 && wid == 0 && lane < W) {
+    __syncthreads();
+    if (wid == 0) {
+        // T(0:j, j) = -beta_j T(0:j, 0:j) g(0:j, j), T(j, j) = beta_j; lane l keeps row l
+        V<P> trow[W];
 #pragma unroll
-        for (int c = 0; c < W; ++c) stm(g.T, g.tps, (long)c * W + lane, trow[c]);
+        for (int q = 0; q < W; ++q) trow[q] = zero<P>();
+#pragma unroll
+        for (int jj = 0; jj < W; ++jj) {
+            if (jj < g.wact) {
+                Acc<P> t = acc_zero<P>();
+#pragma unroll
+                for (int k = 0; k < jj; ++k)
+                    if (lane <= k) acc_fma(t, trow[k], lds_ld<P>(&s_gram[(jj * W + k) * P]));
+                const V<P> bj = lds_ld<P>(&s_info[(jj * 3 + 0) * P]);
+                if (lane < jj) trow[jj] = neg(mul(bj, acc_get(t)));
+                if (lane == jj) trow[jj] = bj;
+            }
+        }
+        if (blockIdx.x == 0 && lane < W) {
+#pragma unroll
+            for (int q = 0; q < W; ++q) stm(g.T, g.tps, (long)q * W + lane, trow[q]);
+        }
+    }
+    // ---- 6. v = x * rho below the diagonal; store the panel (rows from the previous diagonal)
+    const V<P> rc = lds_ld<P>(&s_rho[c * P]);
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const long r = rbase + k * rstride;
+        if (r < hh && c < g.wact) {
+            if (r > off + c && !s_flag[c]) a[k] = mul(a[k], rc);
+            stm(g.A, g.ps, c * g.lda + r, a[k]);
+        }
     }
 }
 
@@ -244,125 +413,129 @@ struct ApplyArgs {
     int nb;
 };
 
-template <int P>
-__device__ __forceinline__ V<P> y_entry(const double *Y, long ldy, long psy, long r, int c, int h, int wact)
-{
-    if (r >= h || c >= wact || r < c) return zero<P>();
-    if (r == c) return from_double<P>(1.0);
-    return ldm<P>(Y, psy, (long)c * ldy + r);
-}
 
-// C := C - Y T^T (Y^T C) over CW columns per workgroup (C's columns, then B's).
-template <int P, int W, int CW>
-__global__ __launch_bounds__(kThreads) void k_apply(ApplyArgs g)
+// C := C - Y T^T (Y^T C).  A workgroup (four waves) takes cpb = 1, 2 or 4 columns of C (then
+// of B); the 4/cpb waves of a column split its rows, so a launch with few columns still fills
+// the GPU; grid-stride over column groups so a capped launch leaves CUs free for a panel.
+// Lanes walk rows (unit-stride limb planes); Y is staged through LDS in chunks of 256 rows
+// shared by the whole workgroup.  Phase 1 keeps W independent lazy accumulators per lane,
+// phase 2 combines the waves of a column and forms U = T^T S, phase 3 updates the column.
+template <int P, int W>
+__global__ __launch_bounds__(kThreads) void k_apply(ApplyArgs g, int cpb)
 {
-    constexpr int CH = 64;       // rows per staged chunk
-    constexpr int CHP = CH + 1;  // padded row stride in LDS
-    constexpr int NO = W * CW;   // entries of S = Y^T C
-    constexpr int NPART = kThreads / NO;
-    static_assert(kThreads % NO == 0, "W*CW must divide the workgroup");
-    __shared__ double sY[W * P * CHP];
-    __shared__ double sC[CW * P * CHP];
-    __shared__ double sR[NPART * NO * P];
-    __shared__ double sU[NO * P];
-
-    const int tid = threadIdx.x;
-    const int col0 = blockIdx.x * CW;
-    double *cbase[CW];
-    long cps[CW];
-#pragma unroll
-    for (int cc = 0; cc < CW; ++cc) {
-        const int gc = col0 + cc;
+    constexpr int CH = 256;  // rows per staged chunk
+    __shared__ double sY[W * P * CH];
+    __shared__ double sS[4 * W * P];  // per wave: lazy sums, then (wave 0 of a column) -U
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int wpc = 4 / cpb;          // waves per column
+    const int cc = wid / wpc, sub = wid % wpc;
+    const int ngroups = (g.nc + g.nb + cpb - 1) / cpb;
+    for (int grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
+        const int gc = grp * cpb + cc;
+        double *col = nullptr;
+        long cps = 0;
         if (gc < g.nc) {
-            cbase[cc] = g.C + (long)gc * g.ldc;
-            cps[cc] = g.psc;
+            col = g.C + (long)gc * g.ldc;
+            cps = g.psc;
         } else if (gc - g.nc < g.nb) {
-            cbase[cc] = g.B + (long)(gc - g.nc) * g.ldb;
-            cps[cc] = g.psb;
-        } else {
-            cbase[cc] = nullptr;
-            cps[cc] = 0;
+            col = g.B + (long)(gc - g.nc) * g.ldb;
+            cps = g.psb;
         }
-    }
-
-    // ---- phase 1: S = Y^T C (lazy accumulation per thread, then a fixed-order tree)
-    const int o = tid % NO, part = tid / NO;
-    const int oi = o / CW, occ = o % CW;
-    Acc<P> acc = acc_zero<P>();
-    int nterm = 0;
-    for (int r0 = 0; r0 < g.h; r0 += CH) {
-        for (int e = tid; e < W * CH; e += kThreads) {
-            const int r = e % CH, c = e / CH;
-            const V<P> y = y_entry<P>(g.Y, g.ldy, g.psy, (long)r0 + r, c, g.h, g.wact);
+        // ---- phase 1: partial S = Y^T c over this wave's rows
+        Acc<P> s[W];
 #pragma unroll
-            for (int k = 0; k < P; ++k) sY[(c * P + k) * CHP + r] = y.x[k];
-        }
-        for (int e = tid; e < CW * CH; e += kThreads) {
-            const int r = e % CH, cc = e / CH;
-            const long gr = (long)r0 + r;
-            V<P> v = zero<P>();
+        for (int i = 0; i < W; ++i) s[i] = acc_zero<P>();
+        int nterm = 0;
+        for (int r0 = 0; r0 < g.h; r0 += CH) {
+            __syncthreads();
+            for (int e = tid; e < W * CH; e += kThreads) {
+                const int r = e % CH, i = e / CH;
+                const V<P> y = y_entry<P>(g.Y, g.ldy, g.psy, (long)r0 + r, i, g.h, g.wact);
 #pragma unroll
-            for (int c2 = 0; c2 < CW; ++c2)
-                if (c2 == cc && cbase[c2] && gr < g.h) v = ldm<P>(cbase[c2], cps[c2], gr);
-#pragma unroll
-            for (int k = 0; k < P; ++k) sC[(cc * P + k) * CHP + r] = v.x[k];
-        }
-        __syncthreads();
-        for (int r = part; r < CH; r += NPART) {
-            V<P> y, c;
-#pragma unroll
-            for (int k = 0; k < P; ++k) {
-                y.x[k] = sY[(oi * P + k) * CHP + r];
-                c.x[k] = sC[(occ * P + k) * CHP + r];
+                for (int k = 0; k < P; ++k) sY[(i * P + k) * CH + r] = y.x[k];
             }
-            acc_fma_step(acc, y, c, nterm++);
-        }
-        __syncthreads();
-    }
-    lds_st(&sR[(part * NO + o) * P], acc_get(acc));
-    __syncthreads();
-    if (tid < NO) {
-        V<P> s = lds_ld<P>(&sR[tid * P]);
-        for (int p2 = 1; p2 < NPART; ++p2) s = add(s, lds_ld<P>(&sR[(p2 * NO + tid) * P]));
-        lds_st(&sR[tid * P], s);
-    }
-    __syncthreads();
-    // ---- phase 2: U = T^T S
-    if (tid < NO) {
-        const int i = tid / CW, cc = tid % CW;
-        Acc<P> u = acc_zero<P>();
-        for (int l = 0; l <= i; ++l) acc_fma(u, ldm<P>(g.T, g.tps, (long)i * W + l), lds_ld<P>(&sR[(l * CW + cc) * P]));
-        lds_st(&sU[tid * P], acc_get(u));
-    }
-    __syncthreads();
-    // ---- phase 3: C -= Y U
-    for (int r0 = 0; r0 < g.h; r0 += CH) {
-        for (int e = tid; e < W * CH; e += kThreads) {
-            const int r = e % CH, c = e / CH;
-            const V<P> y = y_entry<P>(g.Y, g.ldy, g.psy, (long)r0 + r, c, g.h, g.wact);
+            __syncthreads();
+            if (col) {
+                for (int r = sub * 64 + lane; r < CH; r += wpc * 64) {
+                    const long gr = (long)r0 + r;
+                    if (gr < g.h) {
+                        const V<P> cv = ldm<P>(col, cps, gr);
 #pragma unroll
-            for (int k = 0; k < P; ++k) sY[(c * P + k) * CHP + r] = y.x[k];
-        }
-        __syncthreads();
-        for (int e = tid; e < CW * CH; e += kThreads) {
-            const int r = e % CH, cc = e / CH;
-            const long gr = (long)r0 + r;
+                        for (int i = 0; i < W; ++i) {
+                            V<P> y;
 #pragma unroll
-            for (int c2 = 0; c2 < CW; ++c2) {
-                if (c2 == cc && cbase[c2] && gr < g.h) {
-                    Acc<P> t = acc_from(ldm<P>(cbase[c2], cps[c2], gr));
-#pragma unroll
-                    for (int i = 0; i < W; ++i) {
-                        V<P> y;
-#pragma unroll
-                        for (int k = 0; k < P; ++k) y.x[k] = -sY[(i * P + k) * CHP + r];
-                        acc_fma(t, y, lds_ld<P>(&sU[(i * CW + cc) * P]));
+                            for (int k = 0; k < P; ++k) y.x[k] = sY[(i * P + k) * CH + r];
+                            acc_fma_step(s[i], y, cv, nterm);
+                        }
+                        ++nterm;
                     }
-                    stm(cbase[c2], cps[c2], gr, acc_get(t));
                 }
             }
         }
+        // ---- phase 2: wave butterfly (lazy), combine the column's waves, U = T^T S
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+#pragma unroll
+            for (int m = 32; m >= 1; m >>= 1) acc_add_acc(s[i], shfl_xor_acc(s[i], m));
+        }
         __syncthreads();
+        if (lane == 0) {
+#pragma unroll
+            for (int i = 0; i < W; ++i)
+#pragma unroll
+                for (int k = 0; k < P; ++k) sS[(wid * W + i) * P + k] = s[i].s[k];
+        }
+        __syncthreads();
+        V<P> S[W];
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+            Acc<P> t = acc_zero<P>();
+            for (int w = 0; w < wpc; ++w) {
+                Acc<P> o;
+#pragma unroll
+                for (int k = 0; k < P; ++k) o.s[k] = sS[((cc * wpc + w) * W + i) * P + k];
+                acc_add_acc(t, o);
+            }
+            S[i] = acc_get(t);
+        }
+        V<P> ui = zero<P>();
+        if (lane < g.wact) {
+            Acc<P> u = acc_zero<P>();
+#pragma unroll
+            for (int l = 0; l < W; ++l)
+                if (l <= lane) acc_fma(u, ldm<P>(g.T, g.tps, (long)lane * W + l), S[l]);
+            ui = neg(acc_get(u));
+        }
+        V<P> nU[W];  // -U
+#pragma unroll
+        for (int i = 0; i < W; ++i) nU[i] = shfl_md(ui, i);
+        // ---- phase 3: c -= Y U over this wave's rows
+        for (int r0 = 0; r0 < g.h; r0 += CH) {
+            __syncthreads();
+            for (int e = tid; e < W * CH; e += kThreads) {
+                const int r = e % CH, i = e / CH;
+                const V<P> y = y_entry<P>(g.Y, g.ldy, g.psy, (long)r0 + r, i, g.h, g.wact);
+#pragma unroll
+                for (int k = 0; k < P; ++k) sY[(i * P + k) * CH + r] = y.x[k];
+            }
+            __syncthreads();
+            if (col) {
+                for (int r = sub * 64 + lane; r < CH; r += wpc * 64) {
+                    const long gr = (long)r0 + r;
+                    if (gr < g.h) {
+                        Acc<P> t = acc_from(ldm<P>(col, cps, gr));
+#pragma unroll
+                        for (int i = 0; i < W; ++i) {
+                            V<P> y;
+#pragma unroll
+                            for (int k = 0; k < P; ++k) y.x[k] = sY[(i * P + k) * CH + r];
+                            acc_fma(t, y, nU[i]);
+                        }
+                        stm(col, cps, gr, acc_get(t));
+                    }
+                }
+            }
+        }
     }
 }
 
@@ -608,6 +781,16 @@ bool timing_on();
 void timing_begin(hipStream_t s, void **ev);
 void timing_end(hipStream_t s, void *ev, const char *name, int P, double work);
 
+// Side stream and events of the calling host thread on the current device (created on first
+// use, default priority); look-ahead switch and the grid cap of the concurrent update.
+struct SideStream {
+    hipStream_t q;
+    hipEvent_t ev_panel, ev_wide[2];
+};
+SideStream *side_stream();
+bool lookahead_on();
+int apply_grid_cap();
+
 #define MDLS_LAUNCH(NAME, PREC, WORK, KERNEL, GRID, BLOCK, STREAM, ...)                       \
     do {                                                                                     \
         void *ev_ = nullptr;                                                                 \
@@ -619,24 +802,25 @@ void timing_end(hipStream_t s, void *ev, const char *name, int P, double work);
 
 // ============================================================================ host side
 constexpr int kGMax = 256;  // most workgroups one panel launch may use
+constexpr int kCUs = 256;   // compute units of an MI355X
 
 template <int P>
 struct Cfg;
 template <>
 struct Cfg<1> {
-    static constexpr int W = 8, CW = 4, NCI = 16;
+    static constexpr int W = 16, NCI = 16;
 };
 template <>
 struct Cfg<2> {
-    static constexpr int W = 8, CW = 4, NCI = 16;
+    static constexpr int W = 16, NCI = 16;
 };
 template <>
 struct Cfg<4> {
-    static constexpr int W = 4, CW = 4, NCI = 16;
+    static constexpr int W = 8, NCI = 16;
 };
 template <>
 struct Cfg<8> {
-    static constexpr int W = 4, CW = 4, NCI = 8;
+    static constexpr int W = 4, NCI = 8;
 };
 
 inline int leaf_width(int P)
@@ -648,17 +832,6 @@ inline int leaf_width(int P)
     case 8: return Cfg<8>::W;
     }
     return 0;
-}
-
-// rows per thread of the panel kernel (1, 2 or 4); MDLS_PANEL_R overrides the default
-inline int panel_rows_per_thread(int P)
-{
-    const char *e = getenv("MDLS_PANEL_R");
-    if (e) {
-        const int r = atoi(e);
-        if (r == 1 || r == 2 || (r == 4 && P <= 4)) return r;
-    }
-    return (P <= 2) ? 4 : 1;
 }
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -681,7 +854,7 @@ inline Layout layout(int P, int m, int n, int tile)
     };
     L.beta = take(sizeof(double) * (size_t)P * n);
     L.leafT = take(sizeof(double) * (size_t)P * L.W * L.W * L.nleaves);
-    L.gpart = take(sizeof(double) * 2 * kGMax * 2 * L.W * P);
+    L.gpart = take(sizeof(double) * 2 * kGMax * (L.W * L.W + 2 * L.W) * P);
     L.ctr = take(sizeof(unsigned) * (size_t)(L.nleaves + 1));
     L.err = take(sizeof(int) * 4);
     L.yw = take(sizeof(double) * (size_t)P * (m > n ? m : n));
@@ -711,34 +884,105 @@ struct Ctx {
     double *big() const { return (double *)(ws + L.big); }
 };
 
-template <int P, int W, int R>
-void launch_panel(const PanelArgs &a, hipStream_t s)
+struct PanelCfg {
+    int nt, r;
+};
+
+// Threads per workgroup and rows per thread of the panel kernel; MDLS_PANEL_CFG="nt,r"
+// overrides (one of the instantiated pairs).
+inline PanelCfg panel_cfg(int P)
 {
-    double work = 0;
+    PanelCfg d;
+    switch (P) {
+    case 1: d = {512, 8}; break;
+    case 2: d = {512, 8}; break;
+    case 4: d = {256, 4}; break;
+    default: d = {256, 1}; break;
+    }
+    const char *e = getenv("MDLS_PANEL_CFG");
+    if (e) {
+        PanelCfg o{0, 0};
+        if (sscanf(e, "%d,%d", &o.nt, &o.r) == 2) {
+            const bool ok = (P <= 2 && ((o.nt == 512 && o.r == 8) || (o.nt == 512 && o.r == 2))) ||
+                            (P == 4 && o.nt == 256 && (o.r == 4 || o.r == 1)) ||
+                            (P == 8 && o.nt == 256 && (o.r == 1 || o.r == 2));
+            if (ok) d = o;
+        }
+    }
+    return d;
+}
+
+template <int P, int W>
+void launch_panel(const PanelArgs &a, PanelCfg cf, hipStream_t s)
+{
+    double work = a.off ? 2.0 * (a.h + a.off) * a.off * a.wact : 0.0;  // the look-ahead update
     for (int j = 0; j < a.wact; ++j) work += (a.h - j - 1) + 2.0 * (a.wact - j - 1) * (a.h - j);
-    MDLS_LAUNCH("k_panel", P, work, (k_panel<P, W, R>), dim3(a.G), dim3(kThreads), s, a);
+#define MDLS_PANEL_CASE(NT_, R_)                                                                       \
+    if (cf.nt == NT_ && cf.r == R_) {                                                                 \
+        MDLS_LAUNCH("k_panel", P, work, (k_panel<P, W, R_, NT_>), dim3(a.G), dim3(NT_), s, a);        \
+        return;                                                                                       \
+    }
+    if constexpr (P <= 2) {
+        MDLS_PANEL_CASE(512, 8)
+        MDLS_PANEL_CASE(512, 2)
+    } else if constexpr (P == 4) {
+        MDLS_PANEL_CASE(256, 4)
+        MDLS_PANEL_CASE(256, 1)
+    } else {
+        MDLS_PANEL_CASE(256, 1)
+        MDLS_PANEL_CASE(256, 2)
+    }
+#undef MDLS_PANEL_CASE
 }
 
 // Householder QR of A (m x n) in narrow panels; B (nb columns, may be null) receives Q^T B.
 template <int P>
+void launch_apply(const ApplyArgs &aa, int grid_cap, hipStream_t st)
+{
+    constexpr int W = Cfg<P>::W;
+    const int ntot = aa.nc + aa.nb;
+    if (ntot <= 0) return;
+    // columns per workgroup: as many as still leave at least one workgroup per CU
+    const int cpb = (ntot >= 4 * kCUs) ? 4 : (ntot >= 2 * kCUs ? 2 : 1);
+    int grid = (ntot + cpb - 1) / cpb;
+    if (grid_cap > 0 && grid > grid_cap) grid = grid_cap;
+    MDLS_LAUNCH("k_apply", P, 2.0 * aa.h * aa.wact * ntot, (k_apply<P, W>), dim3(grid), dim3(kThreads), st, aa, cpb);
+}
+
+// Householder QR of A (m x n) in narrow panels of W columns; B (nb columns, may be null)
+// receives Q^T B.  Panel l (l > 0) first applies panel l-1 to its own columns (k_panel with
+// off = W); k_apply(l) updates the columns from panel l+2 on, and B.  With look-ahead
+// (default; MDLS_LOOKAHEAD=0 turns it off) k_apply(l) runs on a side stream concurrently with
+// panel l+1:
+//   caller: panel(l) -> [wait apply(l-1)] -> panel(l+1) -> [wait apply(l)] -> panel(l+2) ...
+//   side:   [wait panel(l)] -> apply(l) -> [wait panel(l+1)] -> apply(l+1) ...
+// and its grid is capped so that CUs stay free for the panel's workgroups.
+template <int P>
 void qr_panels(const Ctx<P> &cx, int m, int n, double *A, long lda, long psa, double *B, long ldb, long psb, int nb)
 {
-    constexpr int W = Cfg<P>::W, CW = Cfg<P>::CW;
-    const int R = panel_rows_per_thread(P);
+    constexpr int W = Cfg<P>::W;
+    const PanelCfg cf = panel_cfg(P);
+    const int rows_per_wg = cf.nt / W * cf.r;
     const int nleaves = cx.L.nleaves;
     MDLS_LAUNCH("k_zero", P, 0, k_zero_u32, dim3((nleaves + 1 + 255) / 256), dim3(256), cx.s, cx.ctr(), nleaves + 1);
     MDLS_LAUNCH("k_zero", P, 0, k_zero_u32, dim3(1), dim3(256), cx.s, (unsigned *)cx.err(), 4);
     const long tps = (long)W * W * nleaves;
+    SideStream *ss = (nleaves > 1 && lookahead_on()) ? side_stream() : nullptr;
+    const int cap = ss ? apply_grid_cap() : 0;
     for (int l = 0; l < nleaves; ++l) {
         const int c0 = l * W;
         const int wact = (n - c0 < W) ? (n - c0) : W;
         const int h = m - c0;
+        const int off = (l > 0) ? W : 0;
         PanelArgs pa;
-        pa.A = A + (long)c0 * lda + c0;
+        pa.A = A + (long)c0 * lda + (c0 - off);
         pa.lda = lda;
         pa.ps = psa;
         pa.h = h;
         pa.wact = wact;
+        pa.off = off;
+        pa.Yp = off ? A + (long)(c0 - W) * lda + (c0 - W) : nullptr;
+        pa.Tp = off ? cx.leafT() + (long)(l - 1) * W * W : nullptr;
         pa.beta = cx.beta() + c0;
         pa.bps = n;
         pa.T = cx.leafT() + (long)l * W * W;
@@ -746,38 +990,43 @@ void qr_panels(const Ctx<P> &cx, int m, int n, double *A, long lda, long psa, do
         pa.gpart = cx.gpart();
         pa.gbar = cx.ctr() + l;
         pa.err = cx.err();
-        int G = (h + kThreads * R - 1) / (kThreads * R);
+        int G = (h + off + rows_per_wg - 1) / rows_per_wg;
         if (G < 1) G = 1;
         pa.G = G;
-        if (R == 1)
-            launch_panel<P, W, 1>(pa, cx.s);
-        else if (R == 2)
-            launch_panel<P, W, 2>(pa, cx.s);
-        else {
-            if constexpr (P <= 4) launch_panel<P, W, 4>(pa, cx.s);
-        }
+        if (ss && l >= 2) hipStreamWaitEvent(cx.s, ss->ev_wide[l & 1], 0);  // apply(l-2) updated this panel
+        launch_panel<P, W>(pa, cf, cx.s);
+
+        // the update of everything right of the next panel, and of B
         const int nc = n - c0 - wact;
-        const int ntot = nc + (B ? nb : 0);
-        if (ntot > 0) {
-            ApplyArgs aa;
-            aa.Y = pa.A;
-            aa.ldy = lda;
-            aa.psy = psa;
-            aa.h = h;
-            aa.wact = wact;
-            aa.T = pa.T;
-            aa.tps = tps;
-            aa.C = A + (long)(c0 + wact) * lda + c0;
-            aa.ldc = lda;
-            aa.psc = psa;
-            aa.nc = nc;
-            aa.B = B ? B + c0 : nullptr;
-            aa.ldb = ldb;
-            aa.psb = psb;
-            aa.nb = B ? nb : 0;
-            MDLS_LAUNCH("k_apply", P, 2.0 * h * wact * ntot, (k_apply<P, W, CW>), dim3((ntot + CW - 1) / CW), dim3(kThreads),
-                        cx.s, aa);
+        const int nn = (nc < W) ? nc : W;  // the next panel's columns: updated by panel l+1 itself
+        ApplyArgs aa;
+        aa.Y = A + (long)c0 * lda + c0;
+        aa.ldy = lda;
+        aa.psy = psa;
+        aa.h = h;
+        aa.wact = wact;
+        aa.T = pa.T;
+        aa.tps = tps;
+        aa.C = A + (long)(c0 + wact + nn) * lda + c0;
+        aa.ldc = lda;
+        aa.psc = psa;
+        aa.nc = nc - nn;
+        aa.B = B ? B + c0 : nullptr;
+        aa.ldb = ldb;
+        aa.psb = psb;
+        aa.nb = B ? nb : 0;
+        if (ss) {
+            hipEventRecord(ss->ev_panel, cx.s);
+            hipStreamWaitEvent(ss->q, ss->ev_panel, 0);
+            launch_apply<P>(aa, cap, ss->q);
+            hipEventRecord(ss->ev_wide[l & 1], ss->q);
+        } else {
+            launch_apply<P>(aa, 0, cx.s);
         }
+    }
+    if (ss) {
+        hipStreamWaitEvent(cx.s, ss->ev_wide[(nleaves - 1) & 1], 0);
+        if (nleaves >= 2) hipStreamWaitEvent(cx.s, ss->ev_wide[nleaves & 1], 0);
     }
 }
 

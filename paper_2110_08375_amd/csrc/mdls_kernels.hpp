@@ -63,6 +63,25 @@ __device__ __forceinline__ V<P> shfl_md(const V<P> &v, int src)
     return o;
 }
 
+template <int P>
+__device__ __forceinline__ Acc<P> shfl_xor_acc(const Acc<P> &v, int mask)
+{
+    Acc<P> o;
+#pragma unroll
+    for (int k = 0; k < P; ++k) o.s[k] = __shfl_xor(v.s[k], mask, 64);
+    return o;
+}
+
+// a += b for two lazy accumulators (b's level sums enter as limbs); symmetric in a and b
+template <int P>
+__device__ __forceinline__ void acc_add_acc(Acc<P> &a, const Acc<P> &b)
+{
+    V<P> bv;
+#pragma unroll
+    for (int k = 0; k < P; ++k) bv.x[k] = b.s[k];
+    acc_add(a, bv);
+}
+
 // Butterfly sum over the 64 lanes of a wave.  md add is symmetric in its operands, so
 // every lane ends with the same bits.
 template <int P>

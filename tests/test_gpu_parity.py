@@ -94,19 +94,26 @@ def test_solve_matches_oracle(M, orc, P, m, n, tile, ones):
     assert qerr <= TOL[P] * max(1, k)
 
 
-def test_multi_workgroup_panel(M, orc, monkeypatch):
-    """One row per thread spreads a 700-row panel over three workgroups (grid barrier)."""
-    monkeypatch.setenv("MDLS_PANEL_R", "1")
-    for P in (2, 4):
+@pytest.mark.parametrize("P,cfg", [(2, "512,2"), (4, "256,1"), (8, "256,2"), (8, "256,1")])
+def test_multi_workgroup_panel(M, orc, monkeypatch, P, cfg):
+    """Small workgroups spread a 700-row panel over several workgroups (grid barrier), with
+    and without the concurrent side-stream update."""
+    monkeypatch.setenv("MDLS_PANEL_CFG", cfg)
+    if True:
         m, n, tile = 700, 64, 16
-        print("case multi-wg P=%d" % P, flush=True)
+        print("case multi-wg P=%d cfg=%s" % (P, cfg), flush=True)
         A, xt = mdgen.ls_problem(P, m, n, 55)
         b = orc.rhs_for(A, xt)
         ref = orc.lstsq(A, b)
-        x, info = M.solve(P, to_gpu(A), to_gpu(b), tile)
-        torch.cuda.synchronize()
-        assert int(info.item()) == 0
-        assert md_err(x.cpu().numpy(), ref["x"]) <= TOL[P] * max(1, kappa(A))
+        outs = []
+        for la in ("1", "0"):
+            monkeypatch.setenv("MDLS_LOOKAHEAD", la)
+            x, info = M.solve(P, to_gpu(A), to_gpu(b), tile)
+            torch.cuda.synchronize()
+            assert int(info.item()) == 0
+            assert md_err(x.cpu().numpy(), ref["x"]) <= TOL[P] * max(1, kappa(A))
+            outs.append(x.cpu().numpy())
+        assert np.array_equal(outs[0], outs[1])  # same arithmetic in the same order
 
 
 @pytest.mark.parametrize("P", (2, 4, 8))

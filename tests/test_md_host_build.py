@@ -117,3 +117,25 @@ def test_lazy_dot_product_against_oracle(H, orc, P):
     scale = abs(F(c)) + sum(abs(F(a[:, i]) * F(b[:, i])) for i in range(n))
     assert abs(F(r) - exact) <= 64 * n * Fraction(2) ** (-53 * P) * scale
     assert normalised(r)
+
+
+@pytest.mark.parametrize("P", (4, 8))
+def test_newton_residual_after_exact_cancellation(H, P):
+    """Regression: 1 - b y cancels its top levels exactly; the renormalised residual used to
+    keep a zero limb between nonzero ones (or two overlapping limbs), and truncating it to
+    P/2 limbs lost ~50 bits of the reciprocal.  Inputs found by sweeping seeds."""
+    eps = Fraction(2) ** (-53 * P)
+    worst = Fraction(0)
+    for t in range(200):
+        b = mdgen.md_vector(P, 1, t, 2)[:, 0] * 2.0 ** ((t % 13) * 7 - 42)
+        r = op(H, P, RECIP, b, b)
+        worst = max(worst, abs(F(r) * F(b) - 1))
+        a = mdgen.md_vector(P, 1, t, 4)[:, 0]
+        a = a if a[0] > 0 else -a
+        s = op(H, P, SQRT, a, a)
+        worst = max(worst, abs(F(s) ** 2 - F(a)) / F(a))
+    assert worst <= 2 ** 12 * eps
+    # the seed that exposed it (quad double)
+    if P == 4:
+        b = np.array([47.41589486320882, 2.6195326442484756e-15, -3.3598135411187007e-32, 1.1778734330149813e-48])
+        assert abs(F(op(H, P, RECIP, b, b)) * F(b) - 1) <= 64 * eps
