@@ -9,9 +9,10 @@
 //                 (H_0 ... H_{W-1} = I - Y T Y^T, so the paper's W = -Y T).  The panel's rows
 //                 stay in registers across all its columns; one workgroup reduction (and, when
 //                 the panel spans several workgroups, one grid barrier) per column.
-//     k_apply  -- the trailing update C := C + Y (W^T C) = C - Y T^T (Y^T C) (paper's
-//                 "YWT*C" and "R + YWTC" fused), applied to every column right of the panel and
-//                 to the right-hand side, so Q^T b comes out of the factorisation.
+//     k_apply_s, k_apply_t, k_apply_u -- the trailing update C := C + Y (W^T C) =
+//                 C - Y T^T (Y^T C) (paper's "YWT*C" and "R + YWTC" fused), applied to every
+//                 column right of the panel and to the right-hand side, so Q^T b comes out of
+//                 the factorisation.
 //   Back substitution (Section 2, Algorithm 1):
 //     k_invert -- invert the diagonal tiles (all columns of a tile in parallel, one row step at
 //                 a time);
@@ -87,35 +88,45 @@ __device__ inline void grid_sync(unsigned *ctr, unsigned target, int *err)
 //
 // When off = W the kernel first applies the previous panel's block reflector to its own
 // columns, C := C - Y' T'^T (Y'^T C) over the rows from the previous diagonal down (this is
-// the look-ahead: the rest of the trailing matrix is updated by k_apply concurrently).
+// the look-ahead: the rest of the trailing matrix is updated by the k_apply kernels
+// concurrently).
 //
 // Column j of the panel, x = A(j:h, j) with x1 = a_jj, sigma = sum_{i>j} x_i^2, mu = ||x||:
 // the Householder vector is kept unnormalised as u = gamma (x - mu e1), with
 //   x1 <= 0: gamma = 1,        u1 = x1 - mu, tau = -1/(mu u1),
 //   x1 >  0: gamma = x1 + mu,  u1 = -sigma,  tau = 1/(mu sigma gamma),
 // (both without cancellation, Golub-Van Loan 5.1.1), so that H = I - tau u u^T and the
-// per-column chain needs one reciprocal.  For c > j, with d_c = sum_{i>j} x_i a_ic from the
-// same reduction as sigma, s_c = tau (u1 a_jc + gamma d_c) and the update is a_ic -= s_c
-// gamma x_i (i > j), a_jc -= s_c u1.  At the end of the panel v = u / u1 (scale rho =
-// gamma/u1 on the stored x), beta = tau u1^2 and T are formed.
+// per-column chain needs one square root and one reciprocal.  For c > j, with d_c =
+// sum_{i>j} x_i a_ic from the same reduction as sigma, t_c = u1 a_jc + gamma d_c and the
+// update is a_ic -= tau gamma t_c x_i (i > j), a_jc -= tau u1 t_c.  The stored x becomes
+// v = u / u1 (scale rho = gamma/u1), beta = tau u1^2, and column j of T follows from
+// T(0:j, j) = -beta_j T(0:j, 0:j) (Y(:, 0:j)^T v_j) (Schreiber and Van Loan's compact WY).
 template <int P, int W, int R, int NT>
 __global__ __launch_bounds__(NT) void k_panel(PanelArgs g)
 {
     constexpr int S = NT / W;
     constexpr int NW = NT / 64;
     constexpr int SLOT = (W * W + 2 * W) * P;  // doubles per workgroup exchange slot
-    static_assert(64 % W == 0 && S >= 2 * W, "panel layout");
+    static_assert(64 % W == 0 && S >= 2 * W && NW >= 4, "panel layout");
     __shared__ double s_part[NW * W * W * P];
     __shared__ double s_head[W * P];
-    __shared__ double s_coef[W * P];
-    __shared__ double s_rowj[W * P];
+    __shared__ double s_tot[W * P];       // column j's reduction: sigma (l = j), d_l, Gram sums
+    __shared__ double s_hd[W * P];        // row j: a_jl
     __shared__ double s_mu[P];
-    __shared__ double s_info[W * 3 * P];  // per column: u1, gamma, tau
-    __shared__ double s_gram[W * W * P];  // [j][l]: sum_{i>j} x_j(i) x_l(i), l < j; then g(l, j)
-    __shared__ double s_hrow[W * W * P];  // [j][l]: a_jl when column j is processed
+    __shared__ double s_tau[P];
+    __shared__ double s_ec[W * P];        // gamma t_c
+    __shared__ double s_fc[W * W * P];    // [j][c]: u1 t_c of column j (deferred row-j update)
+    __shared__ double s_info[W * 2 * P];  // per column: u1, tau
+    __shared__ double s_gram[W * W * P];  // [j][l]: sum_{i>j} x_j(i) x_l(i), l < j
+    __shared__ double s_hrow[W * W * P];  // [j][l]: a_jl when column j is processed, l < j
     __shared__ double s_rho[W * P];
+    __shared__ double s_beta[W * P];
+    __shared__ double s_T[W * W * P];     // T, column-major
     __shared__ int s_flag[W];             // sigma == 0
 
+    // The panel is the critical path of the factorisation: its waves take issue priority over
+    // the trailing-update waves that may share their compute unit.
+    __builtin_amdgcn_s_setprio(3);
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int c = tid % W, slot = tid / W;
     const long rstride = (long)g.G * S;
@@ -124,6 +135,52 @@ __global__ __launch_bounds__(NT) void k_panel(PanelArgs g)
     const int off = g.off;
     const long hh = (long)g.h + off;
     unsigned nbar = 0;
+
+    // Off-chain pieces of the compact-WY factor (block 0; beta and T are written by it only).
+    // beta_jj = tau u1^2 (wave 2)
+    auto t_beta = [&](int jj) __attribute__((always_inline)) {
+        V<P> beta = zero<P>();
+        if (!s_flag[jj]) {
+            const V<P> u1 = lds_ld<P>(&s_info[(jj * 2 + 0) * P]);
+            beta = mul(lds_ld<P>(&s_info[(jj * 2 + 1) * P]), mul(u1, u1));
+        }
+        if (lane == 0) {
+            lds_st(&s_beta[jj * P], beta);
+            stm(g.beta, g.bps, jj, beta);
+        }
+    };
+    // lane l < jj: g(l, jj) = y_l^T v_jj = rho_l (a_jj,l + rho_jj gsum_jj,l) (wave 3)
+    auto t_g = [&](int jj) __attribute__((always_inline)) {
+        V<P> gv = zero<P>();
+        if (lane < jj) {
+            const V<P> rl = lds_ld<P>(&s_rho[lane * P]), rj = lds_ld<P>(&s_rho[jj * P]);
+            gv = mul(rl, fma(lds_ld<P>(&s_hrow[(jj * W + lane) * P]), rj, lds_ld<P>(&s_gram[(jj * W + lane) * P])));
+        }
+        return gv;
+    };
+    // lane l < jj: w_l = sum_{l <= k < jj} T(l, k) g(k, jj) (wave 3)
+    auto t_w = [&](int jj, const V<P> &gv) __attribute__((always_inline)) {
+        Acc<P> w = acc_zero<P>();
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            if (k < jj) {
+                const V<P> gk = shfl_md(gv, k);
+                if (lane <= k) acc_fma(w, lds_ld<P>(&s_T[(k * W + lane) * P]), gk);
+            }
+        }
+        return acc_get(w);
+    };
+    // T(0:jj, jj) = -beta_jj w, T(jj, jj) = beta_jj, zero below (wave 3)
+    auto t_store = [&](int jj, const V<P> &w) __attribute__((always_inline)) {
+        const V<P> bj = lds_ld<P>(&s_beta[jj * P]);
+        if (lane < W) {
+            V<P> t = zero<P>();
+            if (lane < jj && !s_flag[jj]) t = neg(mul(bj, w));
+            if (lane == jj) t = bj;
+            lds_st(&s_T[(jj * W + lane) * P], t);
+            stm(g.T, g.tps, (long)jj * W + lane, t);
+        }
+    };
 
     V<P> a[R];
 #pragma unroll
@@ -216,6 +273,19 @@ __global__ __launch_bounds__(NT) void k_panel(PanelArgs g)
         __syncthreads();
     }
 
+    // Per column j the serial chain (reduction, mu, tau) runs in wave 0; the other waves do
+    // the off-chain work between the same workgroup barriers:
+    //   [B1, B2]  wave 0: reduction of the partial sums (and the grid exchange);
+    //             wave 2: beta of column j-1; wave 3: g(l, j-1) (block 0 only)
+    //   [B2, M]   wave 0: mu; wave 1: A_c; wave 2: 1/sigma; wave 3: w = T(:, :j-1) g(:, j-1)
+    //   [M, Tb]   wave 0: tau; wave 1: e_c = gamma t_c, f_c = u1 t_c with t_c = A_c + mu B_c;
+    //             wave 2: rho_j; wave 3: T(:, j-1) = -beta w
+    //   after Tb  every thread: coef_c = tau e_c and the update of its rows below row j.
+    // Row j of the columns c > j (a_jc -= tau f_c) is not needed again inside the panel, so
+    // that update waits for the end of the panel.
+    // values a wave carries across barriers, by role: wave 0 x1^2 + sigma; wave 1 A_c, B_c;
+    // wave 2 1/sigma; wave 3 g, then w
+    V<P> cx = zero<P>(), cy = zero<P>();
     for (int j = 0; j < g.wact; ++j) {
         const long dj = off + j;  // row of the diagonal element of column j
         // ---- 1. one reduction per column: thread (slot, c) sums x_j(i) a_c(i) over its rows i > j:
@@ -236,7 +306,7 @@ __global__ __launch_bounds__(NT) void k_panel(PanelArgs g)
             for (int k = 0; k < P; ++k) s_part[(wid * W + lane) * P + k] = acc.s[k];
         }
         if (blockIdx.x == 0 && slot == dj) lds_st(&s_head[c * P], a[0]);
-        __syncthreads();
+        __syncthreads();  // B1
         if (wid == 0) {
             Acc<P> ta = acc_zero<P>();
             for (int i = lane; i < NW * W; i += 64) {
@@ -275,59 +345,97 @@ __global__ __launch_bounds__(NT) void k_panel(PanelArgs g)
             }
             const V<P> tot = acc_get(ta);
             // lanes l < W now hold tot = total of column l and hd = a_jl
-            // ---- 2. Householder scalars, identical in every lane and every workgroup
-            const V<P> sig = shfl_md(tot, j);
-            const V<P> x1 = shfl_md(hd, j);
-            const bool zs = is_zero(sig);
-            V<P> mu = x1, u1 = zero<P>(), gam = from_double<P>(1.0), tau = zero<P>();
-            if (!zs) {
-                mu = sqrt_md(fma(sig, x1, x1));
-                if (x1.x[0] <= 0.0) {
-                    u1 = sub(x1, mu);
-                    tau = neg(recip(mul(mu, u1)));
-                } else {
-                    gam = add(x1, mu);
-                    u1 = neg(sig);
-                    tau = recip(mul(mul(mu, sig), gam));
-                }
-            }
-            // ---- 3. per-column multipliers (lane c > j)
-            if (lane > j && lane < W) {
-                const V<P> sc = mul(tau, fma(mul(gam, tot), u1, hd));  // tau (u1 a_jc + gamma d_c)
-                lds_st(&s_coef[lane * P], mul(sc, gam));
-                lds_st(&s_rowj[lane * P], mul(sc, u1));
+            if (lane < W) {
+                lds_st(&s_tot[lane * P], tot);
+                lds_st(&s_hd[lane * P], hd);
             }
             if (lane < j) {
                 lds_st(&s_gram[(j * W + lane) * P], tot);
                 lds_st(&s_hrow[(j * W + lane) * P], hd);
             }
-            if (lane == 0) {
-                lds_st(s_mu, mu);
-                lds_st(&s_info[(j * 3 + 0) * P], u1);
-                lds_st(&s_info[(j * 3 + 1) * P], gam);
-                lds_st(&s_info[(j * 3 + 2) * P], tau);
-                s_flag[j] = zs ? 1 : 0;
-            }
+        } else if (blockIdx.x == 0 && j > 0) {
+            if (wid == 2) t_beta(j - 1);
+            if (wid == 3) cx = t_g(j - 1);
         }
         ++nbar;
-        __syncthreads();
-        // ---- 4. reflector j applied to the columns c > j; mu on the diagonal
-        if (!s_flag[j]) {
-            const V<P> mu = lds_ld<P>(s_mu);
-            V<P> ncoef = zero<P>(), rowj = zero<P>();
-            if (c > j) {
-                ncoef = neg(lds_ld<P>(&s_coef[c * P]));
-                rowj = lds_ld<P>(&s_rowj[c * P]);
+        __syncthreads();  // B2
+        // ---- 2. Householder scalars, identical in every lane and every workgroup
+        const V<P> sig = lds_ld<P>(&s_tot[j * P]);
+        const V<P> x1 = lds_ld<P>(&s_hd[j * P]);
+        const bool zs = is_zero(sig);
+        const bool pos = x1.x[0] > 0.0;
+        if (wid == 0) {
+            if (!zs) {
+                cx = fma(sig, x1, x1);
+                const V<P> mu = sqrt_md(cx);
+                if (lane == 0) lds_st(s_mu, mu);
             }
+            if (lane == 0) s_flag[j] = zs ? 1 : 0;
+        } else if (wid == 1) {
+            if (!zs && lane > j && lane < W) {
+                const V<P> d = lds_ld<P>(&s_tot[lane * P]), ajc = lds_ld<P>(&s_hd[lane * P]);
+                if (pos) {  // t_c = (x1 d_c - sigma a_jc) + mu d_c
+                    Acc<P> t = acc_zero<P>();
+                    acc_fma(t, x1, d);
+                    acc_fma(t, neg(sig), ajc);
+                    cx = acc_get(t);
+                    cy = d;
+                } else {  // t_c = (d_c + x1 a_jc) - mu a_jc
+                    cx = fma(d, x1, ajc);
+                    cy = neg(ajc);
+                }
+            }
+        } else if (wid == 2) {
+            if (!zs && pos) cx = recip(sig);
+        } else if (wid == 3 && blockIdx.x == 0 && j > 0) {
+            cx = t_w(j - 1, cx);
+        }
+        __syncthreads();  // M
+        if (wid == 0) {
+            if (!zs) {
+                // tau = 1/(mu (mu - x1)) for x1 <= 0, 1/(mu sigma (x1 + mu)) for x1 > 0; with
+                // E = x1^2 + sigma + mu |x1| both denominators are E or sigma E
+                const V<P> mu = lds_ld<P>(s_mu);
+                const V<P> e = fma(cx, mu, pos ? x1 : neg(x1));
+                const V<P> tau = recip(pos ? mul(sig, e) : e);
+                if (lane == 0) {
+                    lds_st(s_tau, tau);
+                    lds_st(&s_info[(j * 2 + 1) * P], tau);
+                }
+            }
+        } else if (wid == 1) {
+            if (!zs) {
+                const V<P> mu = lds_ld<P>(s_mu);
+                if (lane > j && lane < W) {
+                    const V<P> t = fma(cx, mu, cy);
+                    lds_st(&s_ec[lane * P], pos ? mul(t, add(x1, mu)) : t);
+                    lds_st(&s_fc[(j * W + lane) * P], mul(t, pos ? neg(sig) : sub(x1, mu)));
+                }
+                if (lane == 0) lds_st(&s_info[(j * 2 + 0) * P], pos ? neg(sig) : sub(x1, mu));
+            }
+        } else if (wid == 2) {
+            // rho_j = gamma / u1: -1/(mu - x1) for x1 <= 0, -(x1 + mu)/sigma for x1 > 0
+            V<P> rho = from_double<P>(1.0);
+            if (!zs) {
+                const V<P> mu = lds_ld<P>(s_mu);
+                rho = pos ? neg(mul(add(x1, mu), cx)) : neg(recip(sub(mu, x1)));
+            }
+            if (lane == 0) lds_st(&s_rho[j * P], rho);
+        } else if (wid == 3 && blockIdx.x == 0 && j > 0) {
+            t_store(j - 1, cx);
+        }
+        __syncthreads();  // Tb
+        // ---- 3. reflector j applied to the columns c > j below row j; mu on the diagonal
+        if (!zs) {
+            const V<P> mu = lds_ld<P>(s_mu);
+            V<P> ncoef = zero<P>();
+            if (c > j) ncoef = neg(mul(lds_ld<P>(s_tau), lds_ld<P>(&s_ec[c * P])));
 #pragma unroll
             for (int k = 0; k < R; ++k) {
                 const long r = rbase + k * rstride;
                 const V<P> xk = shfl_md(a[k], src0 + j);  // column j is unchanged below row j
                 if (r == dj) {
-                    if (c == j)
-                        a[k] = mu;
-                    else if (c > j)
-                        a[k] = sub(a[k], rowj);
+                    if (c == j) a[k] = mu;
                 } else if (r > dj && r < hh && c > j) {
                     a[k] = fma(a[k], ncoef, xk);
                 }
@@ -335,70 +443,47 @@ __global__ __launch_bounds__(NT) void k_panel(PanelArgs g)
         }
     }
     __syncthreads();
-    // ---- 5. beta, the normalisation rho = gamma/u1 and T, in wave 0
-    if (wid == 0) {
-        V<P> rho = from_double<P>(1.0), beta = zero<P>();
-        if (lane < g.wact && !s_flag[lane]) {
-            const V<P> u1 = lds_ld<P>(&s_info[(lane * 3 + 0) * P]);
-            const V<P> gam = lds_ld<P>(&s_info[(lane * 3 + 1) * P]);
-            const V<P> tau = lds_ld<P>(&s_info[(lane * 3 + 2) * P]);
-            rho = mul(gam, recip(u1));
-            beta = mul(tau, mul(u1, u1));
-        }
-        if (lane < W) {
-            lds_st(&s_rho[lane * P], rho);
-            lds_st(&s_info[(lane * 3 + 0) * P], beta);  // s_info(j, 0) now holds beta_j
-        }
-        if (blockIdx.x == 0 && lane < g.wact) stm(g.beta, g.bps, lane, beta);
+    // ---- 4. the last column's beta and T column; the deferred row updates; v = x rho below
+    //         the diagonal; store the panel (rows from the previous diagonal)
+    if (blockIdx.x == 0 && g.wact > 0) {
+        if (wid == 2) t_beta(g.wact - 1);
+        if (wid == 3) cx = t_w(g.wact - 1, t_g(g.wact - 1));
     }
-    __syncthreads();
-    if (wid == 0) {
-        // g(l, j) = y_l^T v_j = rho_l (a_jl + rho_j gsum_jl), l < j, written over s_gram(j, l)
-        for (int q = lane; q < W * W; q += 64) {
-            const int gj = q / W, gl = q % W;
-            if (gl < gj && gj < g.wact) {
-                const V<P> rl = lds_ld<P>(&s_rho[gl * P]), rj = lds_ld<P>(&s_rho[gj * P]);
-                lds_st(&s_gram[q * P],
-                       mul(rl, fma(lds_ld<P>(&s_hrow[q * P]), rj, lds_ld<P>(&s_gram[q * P]))));
-            }
-        }
-    }
-    __syncthreads();
-    if (wid == 0) {
-        // T(0:j, j) = -beta_j T(0:j, 0:j) g(0:j, j), T(j, j) = beta_j; lane l keeps row l
-        V<P> trow[W];
-#pragma unroll
-        for (int q = 0; q < W; ++q) trow[q] = zero<P>();
-#pragma unroll
-        for (int jj = 0; jj < W; ++jj) {
-            if (jj < g.wact) {
-                Acc<P> t = acc_zero<P>();
-#pragma unroll
-                for (int k = 0; k < jj; ++k)
-                    if (lane <= k) acc_fma(t, trow[k], lds_ld<P>(&s_gram[(jj * W + k) * P]));
-                const V<P> bj = lds_ld<P>(&s_info[(jj * 3 + 0) * P]);
-                if (lane < jj) trow[jj] = neg(mul(bj, acc_get(t)));
-                if (lane == jj) trow[jj] = bj;
-            }
-        }
-        if (blockIdx.x == 0 && lane < W) {
-#pragma unroll
-            for (int q = 0; q < W; ++q) stm(g.T, g.tps, (long)q * W + lane, trow[q]);
-        }
-    }
-    // ---- 6. v = x * rho below the diagonal; store the panel (rows from the previous diagonal)
     const V<P> rc = lds_ld<P>(&s_rho[c * P]);
 #pragma unroll
     for (int k = 0; k < R; ++k) {
         const long r = rbase + k * rstride;
         if (r < hh && c < g.wact) {
-            if (r > off + c && !s_flag[c]) a[k] = mul(a[k], rc);
+            const long jr = r - off;  // panel row
+            if (jr >= 0 && jr < c) {
+                if (!s_flag[jr])
+                    a[k] = sub(a[k], mul(lds_ld<P>(&s_info[(jr * 2 + 1) * P]), lds_ld<P>(&s_fc[(jr * W + c) * P])));
+            } else if (jr > c && !s_flag[c]) {
+                a[k] = mul(a[k], rc);
+            }
             stm(g.A, g.ps, c * g.lda + r, a[k]);
         }
+    }
+    __syncthreads();
+    if (blockIdx.x == 0 && wid == 3) {
+        if (g.wact > 0) t_store(g.wact - 1, cx);
+        for (int jj = g.wact; jj < W; ++jj)
+            if (lane < W) stm(g.T, g.tps, (long)jj * W + lane, zero<P>());
     }
 }
 
 // ============================================================================ trailing update
+// C := C - Y T^T (Y^T C) for the columns right of the panel (those of C, then those of B, as
+// one index space).  The work is cut into units of four columns (one per wave) by rb rows, so
+// that every launch has many equal units whatever its shape:
+//   k_apply_s -- each unit's partial sums Y^T c over its rows (lazy level sums, not rounded);
+//   k_apply_t -- per column, the partial sums combined in a fixed order into S = Y^T c, and
+//                -U = -T^T S;
+//   k_apply_u -- each unit's rows: c -= Y U.
+// All three walk their units grid-stride, so a capped grid leaves CUs free for a concurrent
+// panel.  Y is staged through LDS per unit; lanes walk rows (unit-stride limb planes).
+constexpr int kRB = 256;  // most rows per unit
+
 struct ApplyArgs {
     const double *Y;  // panel top-left (diagonal) element; Y is unit lower trapezoidal
     long ldy, psy;
@@ -411,129 +496,181 @@ struct ApplyArgs {
     double *B;  // extra columns (right-hand sides), panel's first row
     long ldb, psb;
     int nb;
+    int c0, ncol;  // this launch covers columns c0 .. c0 + ncol - 1 of the (C, B) index space
+    int rb, nrb;   // rows per unit (a multiple of 64, at most kRB) and row blocks
+    double *part;  // [ncol][nrb][W][P] partial sums
+    double *nu;    // [ncol][W][P] -U
 };
 
-
-// C := C - Y T^T (Y^T C).  A workgroup (four waves) takes cpb = 1, 2 or 4 columns of C (then
-// of B); the 4/cpb waves of a column split its rows, so a launch with few columns still fills
-// the GPU; grid-stride over column groups so a capped launch leaves CUs free for a panel.
-// Lanes walk rows (unit-stride limb planes); Y is staged through LDS in chunks of 256 rows
-// shared by the whole workgroup.  Phase 1 keeps W independent lazy accumulators per lane,
-// phase 2 combines the waves of a column and forms U = T^T S, phase 3 updates the column.
-template <int P, int W>
-__global__ __launch_bounds__(kThreads) void k_apply(ApplyArgs g, int cpb)
+// Column gc of this launch (null past the end); its plane stride in *cps.
+__device__ __forceinline__ double *apply_col(const ApplyArgs &g, int gc, long *cps)
 {
-    constexpr int CH = 256;  // rows per staged chunk
-    __shared__ double sY[W * P * CH];
-    __shared__ double sS[4 * W * P];  // per wave: lazy sums, then (wave 0 of a column) -U
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const int wpc = 4 / cpb;          // waves per column
-    const int cc = wid / wpc, sub = wid % wpc;
-    const int ngroups = (g.nc + g.nb + cpb - 1) / cpb;
-    for (int grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
-        const int gc = grp * cpb + cc;
-        double *col = nullptr;
-        long cps = 0;
-        if (gc < g.nc) {
-            col = g.C + (long)gc * g.ldc;
-            cps = g.psc;
-        } else if (gc - g.nc < g.nb) {
-            col = g.B + (long)(gc - g.nc) * g.ldb;
-            cps = g.psb;
+    if (gc >= g.ncol) return nullptr;
+    const int q = g.c0 + gc;
+    if (q < g.nc) {
+        *cps = g.psc;
+        return g.C + (long)q * g.ldc;
+    }
+    *cps = g.psb;
+    return g.B + (long)(q - g.nc) * g.ldb;
+}
+
+template <int P, int W>
+__device__ __forceinline__ void stage_y(const ApplyArgs &g, double *sY, long r0, int tid)
+{
+    for (int e = tid; e < W * g.rb; e += kThreads) {
+        const int r = e % g.rb, i = e / g.rb;
+        const V<P> y = y_entry<P>(g.Y, g.ldy, g.psy, r0 + r, i, g.h, g.wact);
+#pragma unroll
+        for (int k = 0; k < P; ++k) sY[(i * P + k) * kRB + r] = y.x[k];
+    }
+}
+
+// Sum W lazy accumulators over the 64 lanes of a wave; afterwards s[0] of lane l holds the
+// total of accumulator l / (64 / W).  Each level first halves the set a lane keeps (the
+// partner keeps the other half), so W accumulators cost W - 1 + 6 - log2(W) additions
+// instead of 6 W.
+template <int P, int W, int HALF, int M>
+__device__ __forceinline__ void reduce_scatter_level(Acc<P> (&s)[W], int lane)
+{
+    if constexpr (HALF >= 1) {
+        const bool hi = (lane & M) != 0;
+#pragma unroll
+        for (int q = 0; q < HALF; ++q) {
+            Acc<P> mine, give;
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                mine.s[k] = hi ? s[q + HALF].s[k] : s[q].s[k];
+                give.s[k] = hi ? s[q].s[k] : s[q + HALF].s[k];
+            }
+            acc_add_acc(mine, shfl_xor_acc(give, M));
+            s[q] = mine;
         }
-        // ---- phase 1: partial S = Y^T c over this wave's rows
+        reduce_scatter_level<P, W, HALF / 2, M / 2>(s, lane);
+    } else {
+#pragma unroll
+        for (int m = M; m >= 1; m >>= 1) acc_add_acc(s[0], shfl_xor_acc(s[0], m));
+    }
+}
+
+template <int P, int W>
+__device__ __forceinline__ void reduce_scatter(Acc<P> (&s)[W], int lane)
+{
+    static_assert(W >= 1 && W <= 32 && (W & (W - 1)) == 0, "reduce_scatter: W a power of two");
+    reduce_scatter_level<P, W, W / 2, 32>(s, lane);
+}
+
+template <int P, int W>
+__global__ __launch_bounds__(kThreads) void k_apply_s(ApplyArgs g)
+{
+    __shared__ double sY[W * P * kRB];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int ncg = (g.ncol + 3) / 4;
+    const int units = ncg * g.nrb;
+    for (int u = blockIdx.x; u < units; u += gridDim.x) {
+        const int cg = u % ncg, rbk = u / ncg;
+        const long r0 = (long)rbk * g.rb;
+        __syncthreads();
+        stage_y<P, W>(g, sY, r0, tid);
+        __syncthreads();
+        const int gc = cg * 4 + wid;
+        long cps = 0;
+        const double *col = apply_col(g, gc, &cps);
+        if (!col) continue;  // whole wave
         Acc<P> s[W];
 #pragma unroll
         for (int i = 0; i < W; ++i) s[i] = acc_zero<P>();
         int nterm = 0;
-        for (int r0 = 0; r0 < g.h; r0 += CH) {
-            __syncthreads();
-            for (int e = tid; e < W * CH; e += kThreads) {
-                const int r = e % CH, i = e / CH;
-                const V<P> y = y_entry<P>(g.Y, g.ldy, g.psy, (long)r0 + r, i, g.h, g.wact);
+        for (int r = lane; r < g.rb; r += 64) {
+            const long gr = r0 + r;
+            if (gr < g.h) {
+                const V<P> cv = ldm<P>(col, cps, gr);
 #pragma unroll
-                for (int k = 0; k < P; ++k) sY[(i * P + k) * CH + r] = y.x[k];
-            }
-            __syncthreads();
-            if (col) {
-                for (int r = sub * 64 + lane; r < CH; r += wpc * 64) {
-                    const long gr = (long)r0 + r;
-                    if (gr < g.h) {
-                        const V<P> cv = ldm<P>(col, cps, gr);
+                for (int i = 0; i < W; ++i) {
+                    V<P> y;
 #pragma unroll
-                        for (int i = 0; i < W; ++i) {
-                            V<P> y;
-#pragma unroll
-                            for (int k = 0; k < P; ++k) y.x[k] = sY[(i * P + k) * CH + r];
-                            acc_fma_step(s[i], y, cv, nterm);
-                        }
-                        ++nterm;
-                    }
+                    for (int k = 0; k < P; ++k) y.x[k] = sY[(i * P + k) * kRB + r];
+                    acc_fma_step(s[i], y, cv, nterm);
                 }
+                ++nterm;
             }
         }
-        // ---- phase 2: wave butterfly (lazy), combine the column's waves, U = T^T S
+        reduce_scatter<P, W>(s, lane);
+        constexpr int LPI = 64 / W;
+        if (lane % LPI == 0) {
+            double *dst = g.part + (((long)gc * g.nrb + rbk) * W + lane / LPI) * P;
 #pragma unroll
-        for (int i = 0; i < W; ++i) {
-#pragma unroll
-            for (int m = 32; m >= 1; m >>= 1) acc_add_acc(s[i], shfl_xor_acc(s[i], m));
+            for (int k = 0; k < P; ++k) dst[k] = s[0].s[k];
         }
+    }
+}
+
+template <int P, int W>
+__global__ __launch_bounds__(kThreads) void k_apply_t(ApplyArgs g)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int gc = blockIdx.x * 4 + wid; gc < g.ncol; gc += gridDim.x * 4) {
+        // lane q adds the partial sums (b, i) = (q / W + 64 k / W, q % W), then the lanes of
+        // one i are combined
+        Acc<P> t = acc_zero<P>();
+        const double *src = g.part + (long)gc * g.nrb * W * P;
+        for (int q = lane; q < g.nrb * W; q += 64) {
+            Acc<P> o;
+#pragma unroll
+            for (int k = 0; k < P; ++k) o.s[k] = src[(long)q * P + k];
+            acc_add_acc(t, o);
+        }
+#pragma unroll
+        for (int m = W; m < 64; m <<= 1) acc_add_acc(t, shfl_xor_acc(t, m));
+        const V<P> S = acc_get(t);  // lane l: S_(l mod W)
+        Acc<P> u = acc_zero<P>();
+#pragma unroll
+        for (int l = 0; l < W; ++l) {
+            const V<P> sl = shfl_md(S, l);
+            if (l <= lane && lane < g.wact) acc_fma(u, ldm<P>(g.T, g.tps, (long)lane * W + l), sl);
+        }
+        if (lane < W) {
+            const V<P> nv = neg(acc_get(u));
+#pragma unroll
+            for (int k = 0; k < P; ++k) g.nu[((long)gc * W + lane) * P + k] = nv.x[k];
+        }
+    }
+}
+
+template <int P, int W>
+__global__ __launch_bounds__(kThreads) void k_apply_u(ApplyArgs g)
+{
+    __shared__ double sY[W * P * kRB];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int ncg = (g.ncol + 3) / 4;
+    const int units = ncg * g.nrb;
+    for (int u = blockIdx.x; u < units; u += gridDim.x) {
+        const int cg = u % ncg, rbk = u / ncg;
+        const long r0 = (long)rbk * g.rb;
         __syncthreads();
-        if (lane == 0) {
-#pragma unroll
-            for (int i = 0; i < W; ++i)
-#pragma unroll
-                for (int k = 0; k < P; ++k) sS[(wid * W + i) * P + k] = s[i].s[k];
-        }
+        stage_y<P, W>(g, sY, r0, tid);
         __syncthreads();
-        V<P> S[W];
+        const int gc = cg * 4 + wid;
+        long cps = 0;
+        double *col = apply_col(g, gc, &cps);
+        if (!col) continue;  // whole wave
+        V<P> nU[W];
 #pragma unroll
-        for (int i = 0; i < W; ++i) {
-            Acc<P> t = acc_zero<P>();
-            for (int w = 0; w < wpc; ++w) {
-                Acc<P> o;
+        for (int i = 0; i < W; ++i)
 #pragma unroll
-                for (int k = 0; k < P; ++k) o.s[k] = sS[((cc * wpc + w) * W + i) * P + k];
-                acc_add_acc(t, o);
-            }
-            S[i] = acc_get(t);
-        }
-        V<P> ui = zero<P>();
-        if (lane < g.wact) {
-            Acc<P> u = acc_zero<P>();
+            for (int k = 0; k < P; ++k) nU[i].x[k] = g.nu[((long)gc * W + i) * P + k];
+        for (int r = lane; r < g.rb; r += 64) {
+            const long gr = r0 + r;
+            if (gr < g.h) {
+                Acc<P> t = acc_from(ldm<P>(col, cps, gr));
 #pragma unroll
-            for (int l = 0; l < W; ++l)
-                if (l <= lane) acc_fma(u, ldm<P>(g.T, g.tps, (long)lane * W + l), S[l]);
-            ui = neg(acc_get(u));
-        }
-        V<P> nU[W];  // -U
+                for (int i = 0; i < W; ++i) {
+                    V<P> y;
 #pragma unroll
-        for (int i = 0; i < W; ++i) nU[i] = shfl_md(ui, i);
-        // ---- phase 3: c -= Y U over this wave's rows
-        for (int r0 = 0; r0 < g.h; r0 += CH) {
-            __syncthreads();
-            for (int e = tid; e < W * CH; e += kThreads) {
-                const int r = e % CH, i = e / CH;
-                const V<P> y = y_entry<P>(g.Y, g.ldy, g.psy, (long)r0 + r, i, g.h, g.wact);
-#pragma unroll
-                for (int k = 0; k < P; ++k) sY[(i * P + k) * CH + r] = y.x[k];
-            }
-            __syncthreads();
-            if (col) {
-                for (int r = sub * 64 + lane; r < CH; r += wpc * 64) {
-                    const long gr = (long)r0 + r;
-                    if (gr < g.h) {
-                        Acc<P> t = acc_from(ldm<P>(col, cps, gr));
-#pragma unroll
-                        for (int i = 0; i < W; ++i) {
-                            V<P> y;
-#pragma unroll
-                            for (int k = 0; k < P; ++k) y.x[k] = sY[(i * P + k) * CH + r];
-                            acc_fma(t, y, nU[i]);
-                        }
-                        stm(col, cps, gr, acc_get(t));
-                    }
+                    for (int k = 0; k < P; ++k) y.x[k] = sY[(i * P + k) * kRB + r];
+                    acc_fma(t, y, nU[i]);
                 }
+                stm(col, cps, gr, acc_get(t));
             }
         }
     }
@@ -837,8 +974,8 @@ inline int leaf_width(int P)
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t beta, leafT, gpart, ctr, err, yw, big, total;
-    int W, nleaves;
+    size_t beta, leafT, gpart, ctr, err, yw, apart, anu, big, total;
+    int W, nleaves, acols;
 };
 
 inline Layout layout(int P, int m, int n, int tile)
@@ -858,6 +995,10 @@ inline Layout layout(int P, int m, int n, int tile)
     L.ctr = take(sizeof(unsigned) * (size_t)(L.nleaves + 1));
     L.err = take(sizeof(int) * 4);
     L.yw = take(sizeof(double) * (size_t)P * (m > n ? m : n));
+    // trailing update: partial sums and -U of at most acols columns per launch
+    L.acols = n + 1;
+    L.apart = take(sizeof(double) * (size_t)P * L.W * L.acols * ((m + 63) / 64));
+    L.anu = take(sizeof(double) * (size_t)P * L.W * L.acols);
     // back substitution inverses / Gram blocks (P x tile x n) or Q^T B scratch (2 x P x tile x 64)
     const size_t big1 = sizeof(double) * (size_t)P * tile * n;
     const size_t big2 = sizeof(double) * 2 * (size_t)P * tile * 64;
@@ -881,6 +1022,8 @@ struct Ctx {
     unsigned *ctr() const { return (unsigned *)(ws + L.ctr); }
     int *err() const { return (int *)(ws + L.err); }
     double *yw() const { return (double *)(ws + L.yw); }
+    double *apart() const { return (double *)(ws + L.apart); }
+    double *anu() const { return (double *)(ws + L.anu); }
     double *big() const { return (double *)(ws + L.big); }
 };
 
@@ -936,24 +1079,39 @@ void launch_panel(const PanelArgs &a, PanelCfg cf, hipStream_t s)
 }
 
 // Householder QR of A (m x n) in narrow panels; B (nb columns, may be null) receives Q^T B.
+// The trailing update (k_apply_s, k_apply_t, k_apply_u) in launches of at most L.acols
+// columns.  Rows per unit: the largest of 256, 128, 64 that still gives two units per CU.
 template <int P>
-void launch_apply(const ApplyArgs &aa, int grid_cap, hipStream_t st)
+void launch_apply(const Ctx<P> &cx, ApplyArgs aa, int grid_cap, hipStream_t st)
 {
     constexpr int W = Cfg<P>::W;
     const int ntot = aa.nc + aa.nb;
-    if (ntot <= 0) return;
-    // columns per workgroup: as many as still leave at least one workgroup per CU
-    const int cpb = (ntot >= 4 * kCUs) ? 4 : (ntot >= 2 * kCUs ? 2 : 1);
-    int grid = (ntot + cpb - 1) / cpb;
-    if (grid_cap > 0 && grid > grid_cap) grid = grid_cap;
-    MDLS_LAUNCH("k_apply", P, 2.0 * aa.h * aa.wact * ntot, (k_apply<P, W>), dim3(grid), dim3(kThreads), st, aa, cpb);
+    aa.part = cx.apart();
+    aa.nu = cx.anu();
+    for (int c0 = 0; c0 < ntot; c0 += cx.L.acols) {
+        aa.c0 = c0;
+        aa.ncol = (ntot - c0 < cx.L.acols) ? (ntot - c0) : cx.L.acols;
+        const int ncg = (aa.ncol + 3) / 4;
+        int rb = kRB;
+        while (rb > 64 && (long)ncg * ((aa.h + rb - 1) / rb) < 2L * kCUs) rb >>= 1;
+        aa.rb = rb;
+        aa.nrb = (aa.h + rb - 1) / rb;
+        int grid = ncg * aa.nrb, tgrid = ncg;
+        if (grid_cap > 0 && grid > grid_cap) grid = grid_cap;
+        if (grid_cap > 0 && tgrid > grid_cap) tgrid = grid_cap;
+        const double half = (double)aa.h * aa.wact * aa.ncol;
+        MDLS_LAUNCH("k_apply_s", P, half, (k_apply_s<P, W>), dim3(grid), dim3(kThreads), st, aa);
+        MDLS_LAUNCH("k_apply_t", P, 0.5 * aa.wact * (aa.wact + 1) * aa.ncol, (k_apply_t<P, W>), dim3(tgrid),
+                    dim3(kThreads), st, aa);
+        MDLS_LAUNCH("k_apply_u", P, half, (k_apply_u<P, W>), dim3(grid), dim3(kThreads), st, aa);
+    }
 }
 
 // Householder QR of A (m x n) in narrow panels of W columns; B (nb columns, may be null)
 // receives Q^T B.  Panel l (l > 0) first applies panel l-1 to its own columns (k_panel with
-// off = W); k_apply(l) updates the columns from panel l+2 on, and B.  With look-ahead
-// (default; MDLS_LOOKAHEAD=0 turns it off) k_apply(l) runs on a side stream concurrently with
-// panel l+1:
+// off = W); apply(l) (the k_apply kernels) updates the columns from panel l+2 on, and B.  With
+// look-ahead (default; MDLS_LOOKAHEAD=0 turns it off) apply(l) runs on a side stream
+// concurrently with panel l+1:
 //   caller: panel(l) -> [wait apply(l-1)] -> panel(l+1) -> [wait apply(l)] -> panel(l+2) ...
 //   side:   [wait panel(l)] -> apply(l) -> [wait panel(l+1)] -> apply(l+1) ...
 // and its grid is capped so that CUs stay free for the panel's workgroups.
@@ -1018,10 +1176,10 @@ void qr_panels(const Ctx<P> &cx, int m, int n, double *A, long lda, long psa, do
         if (ss) {
             hipEventRecord(ss->ev_panel, cx.s);
             hipStreamWaitEvent(ss->q, ss->ev_panel, 0);
-            launch_apply<P>(aa, cap, ss->q);
+            launch_apply<P>(cx, aa, cap, ss->q);
             hipEventRecord(ss->ev_wide[l & 1], ss->q);
         } else {
-            launch_apply<P>(aa, 0, cx.s);
+            launch_apply<P>(cx, aa, 0, cx.s);
         }
     }
     if (ss) {
