@@ -82,6 +82,78 @@ __device__ inline void grid_sync(unsigned *ctr, unsigned target, int *err)
     __threadfence();
 }
 
+// Sum of NA lazy accumulators per lane over the row-slot bits of a wave (lane masks 32, 16,
+// ..., MMIN): while a lane holds two or more accumulators each level halves the set (the
+// partner keeps the other half), then plain butterfly levels follow.  Lane l keeps
+// slot_scatter_kept<W>() accumulators, starting at index slot_scatter_index<W>(l); equal
+// totals sit on the lanes that differ only in slot_plain_mask bits.
+template <int P, int NA, int NH, int MMIN, int M>
+__device__ __forceinline__ void slot_scatter(Acc<P> (&s)[NA], int lane)
+{
+    if constexpr (M >= MMIN) {
+        if constexpr (NH >= 2) {
+            constexpr int HALF = NH / 2;
+            const bool hi = (lane & M) != 0;
+#pragma unroll
+            for (int q = 0; q < HALF; ++q) {
+                Acc<P> mine, give;
+#pragma unroll
+                for (int k = 0; k < P; ++k) {
+                    mine.s[k] = hi ? s[q + HALF].s[k] : s[q].s[k];
+                    give.s[k] = hi ? s[q].s[k] : s[q + HALF].s[k];
+                }
+                acc_add_acc(mine, shfl_xor_acc(give, M));
+                s[q] = mine;
+            }
+            slot_scatter<P, NA, HALF, MMIN, M / 2>(s, lane);
+        } else {
+            acc_add_acc(s[0], shfl_xor_acc(s[0], M));
+            slot_scatter<P, NA, NH, MMIN, M / 2>(s, lane);
+        }
+    }
+}
+
+template <int W>
+constexpr int slot_levels()
+{
+    int n = 0;
+    for (int m = 32; m >= W; m >>= 1) ++n;
+    return n;
+}
+
+template <int W>
+constexpr int slot_scatter_kept()
+{
+    int na = W;
+    for (int t = 0; t < slot_levels<W>() && na >= 2; ++t) na /= 2;
+    return na;
+}
+
+template <int W, int MMIN, int M>
+constexpr int slot_plain_mask()
+{
+    int na = W, mask = 0;
+    for (int m = M; m >= MMIN; m >>= 1) {
+        if (na >= 2)
+            na /= 2;
+        else
+            mask |= m;
+    }
+    return mask;
+}
+
+// first accumulator index kept by lane l after slot_scatter over masks 32 .. W
+template <int W>
+__device__ __forceinline__ int slot_scatter_index(int lane)
+{
+    int idx = 0, na = W;
+    for (int m = 32; m >= W && na >= 2; m >>= 1) {
+        na /= 2;
+        if (lane & m) idx += na;
+    }
+    return idx;
+}
+
 // Thread (slot, c) of workgroup b holds column c of rows b*S + slot + k*G*S, k < R, where
 // S = NT/W row slots per workgroup: the W threads of a row are consecutive lanes.  Rows are
 // counted from `off` rows above the panel's diagonal.
@@ -189,7 +261,8 @@ __global__ __launch_bounds__(NT) void k_panel(PanelArgs g)
         a[k] = (r < hh && c < g.wact) ? ldm<P>(g.A, g.ps, c * g.lda + r) : zero<P>();
     }
 
-    // ---- 0. apply the previous panel's reflectors to this panel (look-ahead update)
+    // ---- 0. apply the previous panel's reflectors to this panel (look-ahead update):
+    //         S = Y'^T C (W x W), -U = -T'^T S, C += Y' (-U)
     if (off) {
         Acc<P> sacc[W];
 #pragma unroll
@@ -203,59 +276,74 @@ __global__ __launch_bounds__(NT) void k_panel(PanelArgs g)
                     acc_fma_step(sacc[i], y_entry<P>(g.Yp, g.lda, g.ps, r, i, (int)hh, W), a[k], k);
             }
         }
+        // sum over the wave's row slots; lane (.., c) ends with NF accumulators of column c
+        constexpr int NF = slot_scatter_kept<W>();
+        slot_scatter<P, W, W, W, 32>(sacc, lane);
+        if ((lane & slot_plain_mask<W, W, 32>()) == 0) {
+            const int i0 = slot_scatter_index<W>(lane);
 #pragma unroll
-        for (int i = 0; i < W; ++i) {
+            for (int f = 0; f < NF; ++f)
 #pragma unroll
-            for (int m = W; m < 64; m <<= 1) acc_add_acc(sacc[i], shfl_xor_acc(sacc[i], m));
-            if (lane < W) {
-#pragma unroll
-                for (int k = 0; k < P; ++k) s_part[((wid * W + i) * W + lane) * P + k] = sacc[i].s[k];
-            }
+                for (int k = 0; k < P; ++k) s_part[((wid * W + i0 + f) * W + c) * P + k] = sacc[f].s[k];
         }
         __syncthreads();
+        // pairs q = (i, cc) = (q / W, q % W); LP lanes per pair when W^2 < 64
+        constexpr int WW = W * W;
+        constexpr int LP = (WW < 64) ? 64 / WW : 1;
         if (wid == 0) {
-            // pairs (i, cc) = (q / W, q % W) for q = lane, lane + 64, ...
-            for (int q = lane; q < W * W; q += 64) {
+            for (int q0 = 0; q0 < WW; q0 += 64) {
+                const int q = q0 + lane % (WW < 64 ? WW : 64), sub = (WW < 64) ? lane / WW : 0;
                 Acc<P> t = acc_zero<P>();
-                for (int w = 0; w < NW; ++w) {
+                for (int w = sub; w < NW; w += LP) {
                     Acc<P> o;
 #pragma unroll
-                    for (int k = 0; k < P; ++k) o.s[k] = s_part[(w * W * W + q) * P + k];
+                    for (int k = 0; k < P; ++k) o.s[k] = s_part[(w * WW + q) * P + k];
                     acc_add_acc(t, o);
                 }
-                if (g.G > 1) {
-                    double *mine = g.gpart + (size_t)((nbar & 1) * g.G + blockIdx.x) * SLOT;
 #pragma unroll
-                    for (int k = 0; k < P; ++k) st_coherent(mine + q * P + k, t.s[k]);
-                } else {
+                for (int m = WW; m < 64; m <<= 1) acc_add_acc(t, shfl_xor_acc(t, m));
+                if (g.G > 1) {
+                    if (sub == 0) {
+                        double *mine = g.gpart + (size_t)((nbar & 1) * g.G + blockIdx.x) * SLOT;
+#pragma unroll
+                        for (int k = 0; k < P; ++k) st_coherent(mine + q * P + k, t.s[k]);
+                    }
+                } else if (sub == 0) {
                     lds_st(&s_gram[q * P], acc_get(t));
                 }
             }
             if (g.G > 1) {
                 grid_sync(g.gbar, (nbar + 1) * (unsigned)g.G, g.err);
                 const double *base = g.gpart + (size_t)((nbar & 1) * g.G) * SLOT;
-                for (int q = lane; q < W * W; q += 64) {
+                for (int q0 = 0; q0 < WW; q0 += 64) {
+                    const int q = q0 + lane % (WW < 64 ? WW : 64), sub = (WW < 64) ? lane / WW : 0;
                     Acc<P> t = acc_zero<P>();
-                    for (int b = 0; b < g.G; ++b) {
+                    for (int b = sub; b < g.G; b += LP) {
                         Acc<P> o;
 #pragma unroll
                         for (int k = 0; k < P; ++k) o.s[k] = ld_coherent(base + (size_t)b * SLOT + q * P + k);
                         acc_add_acc(t, o);
                     }
-                    lds_st(&s_gram[q * P], acc_get(t));
+#pragma unroll
+                    for (int m = WW; m < 64; m <<= 1) acc_add_acc(t, shfl_xor_acc(t, m));
+                    if (sub == 0) lds_st(&s_gram[q * P], acc_get(t));
                 }
             }
         }
         ++nbar;
         __syncthreads();
-        // U(i, cc) = sum_{l<=i} T'(l, i) S(l, cc), negated, into s_hrow (scratch)
+        // -U(i, cc) = -sum_{l<=i} T'(l, i) S(l, cc) into s_hrow (scratch); the LP lanes of a
+        // pair split the sum over l
         if (wid == 0) {
-            for (int q = lane; q < W * W; q += 64) {
+            for (int q0 = 0; q0 < WW; q0 += 64) {
+                const int q = q0 + lane % (WW < 64 ? WW : 64), sub = (WW < 64) ? lane / WW : 0;
                 const int i = q / W, cc = q % W;
                 Acc<P> u = acc_zero<P>();
-                for (int l = 0; l <= i; ++l)
+                for (int l = sub; l <= i; l += LP)
                     acc_fma(u, ldm<P>(g.Tp, g.tps, (long)i * W + l), lds_ld<P>(&s_gram[(l * W + cc) * P]));
-                lds_st(&s_hrow[q * P], neg(acc_get(u)));
+#pragma unroll
+                for (int m = WW; m < 64; m <<= 1) acc_add_acc(u, shfl_xor_acc(u, m));
+                if (sub == 0) lds_st(&s_hrow[q * P], neg(acc_get(u)));
             }
         }
         __syncthreads();
@@ -623,16 +711,25 @@ __global__ __launch_bounds__(kThreads) void k_apply_t(ApplyArgs g)
 #pragma unroll
         for (int m = W; m < 64; m <<= 1) acc_add_acc(t, shfl_xor_acc(t, m));
         const V<P> S = acc_get(t);  // lane l: S_(l mod W)
-        Acc<P> u = acc_zero<P>();
+        // U_i = sum_{l <= i} T(l, i) S_l: lane p = i W + l (+ 64 k) forms one product, then
+        // the W lanes of an i are summed
+        constexpr int NQ = (W * W + 63) / 64;
+        Acc<P> u[NQ];
 #pragma unroll
-        for (int l = 0; l < W; ++l) {
-            const V<P> sl = shfl_md(S, l);
-            if (l <= lane && lane < g.wact) acc_fma(u, ldm<P>(g.T, g.tps, (long)lane * W + l), sl);
-        }
-        if (lane < W) {
-            const V<P> nv = neg(acc_get(u));
+        for (int k = 0; k < NQ; ++k) u[k] = acc_zero<P>();
+        const int l = lane % W;
+        const V<P> sl = shfl_md(S, l);
 #pragma unroll
-            for (int k = 0; k < P; ++k) g.nu[((long)gc * W + lane) * P + k] = nv.x[k];
+        for (int k = 0; k < NQ; ++k) {
+            const int i = (lane + 64 * k) / W;
+            if (l <= i && i < g.wact) acc_fma(u[k], ldm<P>(g.T, g.tps, (long)i * W + l), sl);
+#pragma unroll
+            for (int m = 1; m < W; m <<= 1) acc_add_acc(u[k], shfl_xor_acc(u[k], m));
+            if (l == 0 && i < W) {
+                const V<P> nv = neg(acc_get(u[k]));
+#pragma unroll
+                for (int q = 0; q < P; ++q) g.nu[((long)gc * W + i) * P + q] = nv.x[q];
+            }
         }
     }
 }
@@ -1037,9 +1134,9 @@ inline PanelCfg panel_cfg(int P)
 {
     PanelCfg d;
     switch (P) {
-    case 1: d = {512, 8}; break;
-    case 2: d = {512, 8}; break;
-    case 4: d = {256, 4}; break;
+    case 1: d = {512, 2}; break;
+    case 2: d = {512, 2}; break;
+    case 4: d = {256, 1}; break;
     default: d = {256, 1}; break;
     }
     const char *e = getenv("MDLS_PANEL_CFG");
