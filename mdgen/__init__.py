@@ -209,6 +209,45 @@ def upper_triangular(P: int, n: int, seed: int, well_conditioned: bool = False, 
     return a
 
 
+def upper_triangular_exact(P: int, n: int, seed: int, device=None):
+    """Upper-triangular R (P, n, n) and b = R * ones (P, n) with b exact by construction.
+
+    Only limb 0 is nonzero.  Off-diagonal entries are uniforms rounded to multiples of 2**-25
+    and scaled by 2**-s, s = ceil(log2 n); the diagonal is 1 + (u + 1)/2 rounded to a multiple
+    of 2**-25, in [1, 2].  Every entry is a multiple of 2**-(25 + s) and every partial row sum
+    is below 3, so for s <= 26 each row sum is exact in one double whatever the summation
+    order, and the solution of R x = b is exactly the all-ones vector.  ||D^-1 N||_inf <=
+    n 2**-s <= 1 keeps R well conditioned (the well-conditioned variant of the paper's
+    back-substitution test, Section 4.1).
+    """
+    s = math.ceil(math.log2(n)) if n > 1 else 0
+    assert s <= 26, "row sums would no longer be exact"
+    lead = uniform(seed, STREAM_A, n * n, 0, device=device).reshape(n, n)  # [col, row]
+    d = uniform(seed, STREAM_DIAG, n, 0, device=device)
+    if device is None:
+        q = np.round(lead * 2.0 ** 25) * 2.0 ** (-25 - s)
+        i = np.arange(n)
+        q = np.where(i[None, :] < i[:, None], q, 0.0)
+        q[i, i] = 1.0 + np.round((d + 1.0) * 2.0 ** 24) * 2.0 ** -25
+        R = np.zeros((P, n, n), dtype=np.float64)
+        R[0] = q
+        bv = np.zeros((P, n), dtype=np.float64)
+        bv[0] = q.sum(axis=0)
+        return R, bv
+    import torch
+
+    q = torch.round(lead * 2.0 ** 25) * 2.0 ** (-25 - s)
+    i = torch.arange(n, device=device)
+    q.mul_((i[None, :] < i[:, None]).to(torch.float64))
+    q[i, i] = 1.0 + torch.round((d + 1.0) * 2.0 ** 24) * 2.0 ** -25
+    R = torch.zeros((P, n, n), dtype=torch.float64, device=device)
+    R[0] = q
+    del q, lead
+    bv = torch.zeros((P, n), dtype=torch.float64, device=device)
+    bv[0] = R[0].sum(dim=0)
+    return R, bv
+
+
 def ls_problem(P: int, m: int, n: int, seed: int, ones_solution: bool = False, device=None):
     """A (P, n, m) and x_true (P, n) for a least-squares test problem."""
     A = md_uniform(P, m, n, seed, STREAM_A, device=device)

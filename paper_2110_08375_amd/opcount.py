@@ -39,6 +39,13 @@ def ls_double_ops(p: int, m: int, n: int) -> float:
     return (wa + wm) * ls_md_fmas(m, n) + 3.0 * n * wd
 
 
+def backsub_double_ops(p: int, n: int) -> float:
+    """Back substitution of an n x n triangular system: n(n-1)/2 md multiply-adds and n divisions
+    (the algorithmic count; the tile inversions the method adds are not counted)."""
+    wa, wm, wd = weights(p)
+    return (wa + wm) * n * (n - 1) / 2.0 + n * wd
+
+
 def md_fma_double_ops(p: int) -> int:
     wa, wm, _ = weights(p)
     return wa + wm

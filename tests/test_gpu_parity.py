@@ -232,3 +232,36 @@ def test_full_size_recovers_x_true(M, orc, P, m, n, tile):
     err = md_err(x.cpu().numpy(), xt)
     report("full", err, TOL[P] * max(1, k))
     assert err <= TOL[P] * max(1.0, k)
+
+
+def test_backsub_full_size_exact_rhs(M):
+    """Back substitution at the largest size of the paper's back-substitution tests (upper
+    triangular, quad double, n = 17 920, tile 256, Section 4.1): b = R * ones is exact by
+    construction, so x must be all ones to the qd tolerance (kappa_inf(R) < 10 here)."""
+    from fractions import Fraction
+
+    from paper_2110_08375_amd import opcount
+
+    P, n, tile = 4, 17920, 256
+    print("case backsub full-size P=4 n=17920 tile=256", flush=True)
+    R, b = mdgen.upper_triangular_exact(P, n, 11, device=dev())
+    ws = M.workspace(P, n, n, tile, dev())
+    info = torch.zeros(1, dtype=torch.int32, device=dev())
+    ms = []
+    for _ in range(2):
+        x = b.clone()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        M.backsub(P, R, x, tile, ws=ws, info=info)
+        e1.record()
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    assert int(info.item()) == 0
+    xh = x.cpu().numpy()
+    err = md_err(xh, mdgen.md_ones(P, n))
+    tf = opcount.backsub_double_ops(P, n) / (ms[-1] * 1e-3) / 1e12
+    print("backsub n=17920 qd: %.3f ms, %.3f Table-1 TFLOP/s, err %.3e" % (ms[-1], tf, err), flush=True)
+    assert err <= TOL[P] * 10
+    for i in range(0, n, 997):  # exact check of a sample
+        v = sum(Fraction(float(xh[k, i])) for k in range(P))
+        assert abs(v - 1) <= Fraction(TOL[P] * 10)

@@ -55,3 +55,21 @@ def test_batch_shapes_ranges():
     assert len(sh) == 512
     for m, n in sh:
         assert 32 <= m <= 512 and 16 <= n <= m
+
+
+def test_upper_triangular_exact_rhs_is_exact():
+    """b = R * ones holds exactly (rational check), with the numpy and torch backends equal."""
+    from fractions import Fraction
+
+    import torch
+
+    for n in (5, 40, 129):
+        R, b = mdgen.upper_triangular_exact(4, n, 7)
+        assert np.all(R[1:] == 0.0) and np.all(b[1:] == 0.0)
+        for row in range(n):
+            exact = sum(Fraction(float(R[0, col, row])) for col in range(n))
+            assert Fraction(float(b[0, row])) == exact
+        assert np.all(np.diag(R[0]) >= 1.0) and np.all(np.diag(R[0]) <= 2.0)
+        assert np.all(np.tril(R[0].T, -1) == 0.0)
+        Rt, bt = mdgen.upper_triangular_exact(4, n, 7, device="cpu")
+        assert np.array_equal(Rt.numpy(), R) and np.array_equal(bt.numpy(), b)
