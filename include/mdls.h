@@ -12,7 +12,8 @@
  * of doubles, most significant limb first.  Plane k starts ld * cols doubles after plane
  * k - 1 and is column-major with leading dimension ld >= rows.  A vector of length L is P
  * planes of L doubles.  Every pointer below is a DEVICE pointer.  The caller owns every
- * buffer; the library never allocates device memory, frees or synchronises.  Work is enqueued
+ * buffer; the library never allocates device memory or frees, and synchronises only in the
+ * set-up and tuning calls that say so (mdls_batch_plan, mdls_batch_autotune).  Work is enqueued
  * on the caller's stream; the QR additionally forks part of each trailing update onto a
  * side stream owned by the calling host thread (created once per device on first use, default
  * priority) and joins it back with events before returning, so the caller's stream orders
@@ -109,6 +110,57 @@ int mdls_solve(int p, int m, int n, int tile, double *A, int lda, double *b, dou
 
 /* Static text for a status code. */
 const char *mdls_status_string(int status);
+
+/*
+ * Batched least squares: many independent problems of uneven sizes solved in one
+ * persistent launch (the paper's least-squares solve, Sections 2-3, per problem; its
+ * uneven-size workloads, Section 4).  p is 2 (dd) or 4 (qd); every problem has
+ * 1 <= n <= m <= 512.  Problem i's A is P planes of m x n (ld m, plane stride m n) at
+ * A + a_off, its b P planes of m at b + b_off, its x P planes of n at x + x_off (offsets
+ * in doubles).  A and b are overwritten (factors, Q^T b) as by mdls_solve.
+ *
+ *   mdls_batch_workspace_bytes(p, count)   workspace for a batch of count problems (0 if
+ *                              p or count is invalid).
+ *   mdls_batch_plan(p, count, h_desc, ws, ws_bytes, stream)
+ *                              validates the HOST array h_desc and writes the processing
+ *                              order (largest m n^2 first) into the workspace.  A set-up
+ *                              call: it copies host to device and synchronises the stream,
+ *                              so it must not be captured into a graph.  -3 if any
+ *                              descriptor is invalid.
+ *   mdls_solve_batched(p, count, A, b, x, variant, ws, ws_bytes, d_info, d_times, stream)
+ *                              solves the planned batch: a counter reset and one persistent
+ *                              kernel on `stream`, nothing else (graph-capturable; the
+ *                              workspace keeps the plan).  variant selects the kernel shape
+ *                              (0 <= variant < mdls_batch_variants(p)).  d_info (count device
+ *                              ints) receives each problem's status as *d_info of
+ *                              mdls_solve; d_times (2 count device long longs, or null) the
+ *                              start and end of each problem in wall-clock ticks
+ *                              (mdls_wall_clock_khz).
+ *   mdls_batch_variants(p)     number of kernel variants (0 if p is not supported).
+ *   mdls_batch_autotune(p, count, A_src, b_src, a_len, b_len, A, b, x, ws, ws_bytes, d_info,
+ *                       ms, stream)
+ *                              the project's autotuner: for every variant, copies the pristine
+ *                              A_src, b_src (a_len, b_len doubles) into A, b and times one
+ *                              warm and one timed solve with events; ms (host, one float per
+ *                              variant, or null) receives the times.  Synchronises the
+ *                              stream.  Returns the fastest variant (>= 0) or a status < 0.
+ *   mdls_wall_clock_khz(&khz)  tick rate of the d_times clock on the current device.
+ */
+typedef struct {
+    int m, n;
+    long long a_off, b_off, x_off;
+} mdls_batch_desc;
+
+size_t mdls_batch_workspace_bytes(int p, int count);
+int mdls_batch_plan(int p, int count, const mdls_batch_desc *h_desc, void *ws, size_t ws_bytes,
+                    hipStream_t stream);
+int mdls_solve_batched(int p, int count, double *A, double *b, double *x, int variant, void *ws,
+                       size_t ws_bytes, int *d_info, long long *d_times, hipStream_t stream);
+int mdls_batch_variants(int p);
+int mdls_batch_autotune(int p, int count, const double *A_src, const double *b_src, size_t a_len,
+                        size_t b_len, double *A, double *b, double *x, void *ws, size_t ws_bytes,
+                        int *d_info, float *ms, hipStream_t stream);
+int mdls_wall_clock_khz(int *khz);
 
 /*
  * Per-kernel device timing, as the paper reports per-kernel times (Section 4, kernel time

@@ -9,18 +9,26 @@ from .mdls import (  # noqa: F401
     MDLS_F64,
     MDLS_OD,
     MDLS_QD,
+    BatchDesc,
     apply_qt,
     backsub,
+    batch_autotune,
+    batch_descs,
+    batch_plan,
+    batch_variants,
+    batch_workspace,
     form_w,
     lib,
     max_rows,
     qr,
     solve,
+    solve_batched,
     status_string,
     timing_enable,
     timing_kernels,
     timing_query,
     timing_reset,
+    wall_clock_khz,
     workspace,
     workspace_bytes,
 )

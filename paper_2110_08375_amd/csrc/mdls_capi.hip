@@ -1,5 +1,6 @@
 // mdls_capi.hip -- the C ABI declared in mdls.h: argument checks on the host, then the
 // per-precision drivers (instantiated in mdls_p1/2/4/8.hip).
+#include <algorithm>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -12,6 +13,8 @@ MDLS_FOR_PRECISION(extern, 1)
 MDLS_FOR_PRECISION(extern, 2)
 MDLS_FOR_PRECISION(extern, 4)
 MDLS_FOR_PRECISION(extern, 8)
+MDLS_BATCH_FOR_PRECISION(extern, 2)
+MDLS_BATCH_FOR_PRECISION(extern, 4)
 }  // namespace mdls_impl
 
 using namespace mdls_impl;
@@ -242,6 +245,111 @@ int mdls_solve(int p, int m, int n, int tile, double *A, int lda, double *b, dou
     if (!d_info) return -11;
     if (m > mdls_max_rows(p)) return MDLS_EUNSUPPORTED;
     return dispatch<SolveF>(p, m, n, tile, A, lda, b, x, ws, d_info, stream);
+}
+
+size_t mdls_batch_workspace_bytes(int p, int count)
+{
+    if (batch_variants(p) == 0 || count < 1) return 0;
+    return batch_layout(p, count).total;
+}
+
+int mdls_batch_variants(int p) { return batch_variants(p); }
+
+int mdls_batch_plan(int p, int count, const mdls_batch_desc *h_desc, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    if (batch_variants(p) == 0) return -1;
+    if (count < 1) return -2;
+    if (!h_desc) return -3;
+    if (!ws) return -4;
+    if (ws_bytes < mdls_batch_workspace_bytes(p, count)) return -5;
+    std::vector<BatchDesc> plan((size_t)count);
+    for (int i = 0; i < count; ++i) {
+        const mdls_batch_desc &d = h_desc[i];
+        if (d.n < 1 || d.m < d.n || d.m > kBatchRows || d.a_off < 0 || d.b_off < 0 || d.x_off < 0) return -3;
+        plan[(size_t)i] = BatchDesc{d.m, d.n, d.a_off, d.b_off, d.x_off, i, 0};
+    }
+    // longest processing time first: the largest m n^2 start first
+    std::stable_sort(plan.begin(), plan.end(), [](const BatchDesc &x, const BatchDesc &y) {
+        return (double)x.m * x.n * x.n > (double)y.m * y.n * y.n;
+    });
+    const BatchLayout L = batch_layout(p, count);
+    if (hipMemcpyAsync((char *)ws + L.plan, plan.data(), sizeof(BatchDesc) * plan.size(), hipMemcpyHostToDevice,
+                       stream) != hipSuccess)
+        return MDLS_EHIP;
+    return hipStreamSynchronize(stream) == hipSuccess ? 0 : MDLS_EHIP;
+}
+
+int mdls_solve_batched(int p, int count, double *A, double *b, double *x, int variant, void *ws, size_t ws_bytes,
+                       int *d_info, long long *d_times, hipStream_t stream)
+{
+    if (batch_variants(p) == 0) return -1;
+    if (count < 1) return -2;
+    if (!A) return -3;
+    if (!b) return -4;
+    if (!x) return -5;
+    if (variant < 0 || variant >= batch_variants(p)) return -6;
+    if (!ws) return -7;
+    if (ws_bytes < mdls_batch_workspace_bytes(p, count)) return -8;
+    if (!d_info) return -9;
+    switch (p) {
+    case 2: return batch_solve_t<2>(count, A, b, x, variant, ws, d_info, d_times, stream);
+    case 4: return batch_solve_t<4>(count, A, b, x, variant, ws, d_info, d_times, stream);
+    }
+    return MDLS_EUNSUPPORTED;
+}
+
+int mdls_batch_autotune(int p, int count, const double *A_src, const double *b_src, size_t a_len, size_t b_len,
+                        double *A, double *b, double *x, void *ws, size_t ws_bytes, int *d_info, float *ms,
+                        hipStream_t stream)
+{
+    if (batch_variants(p) == 0) return -1;
+    if (count < 1) return -2;
+    if (!A_src) return -3;
+    if (!b_src) return -4;
+    if (!A) return -7;
+    if (!b) return -8;
+    if (!x) return -9;
+    if (!ws) return -10;
+    if (ws_bytes < mdls_batch_workspace_bytes(p, count)) return -11;
+    if (!d_info) return -12;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return MDLS_EHIP;
+    int best = -1;
+    float best_ms = 0.0f;
+    int rc = 0;
+    for (int v = 0; v < batch_variants(p) && rc == 0; ++v) {
+        float t = 0.0f;
+        for (int rep = 0; rep < 2 && rc == 0; ++rep) {  // the first run warms up
+            if (hipMemcpyAsync(A, A_src, a_len * sizeof(double), hipMemcpyDeviceToDevice, stream) != hipSuccess ||
+                hipMemcpyAsync(b, b_src, b_len * sizeof(double), hipMemcpyDeviceToDevice, stream) != hipSuccess ||
+                hipEventRecord(e0, stream) != hipSuccess) {
+                rc = MDLS_EHIP;
+                break;
+            }
+            rc = mdls_solve_batched(p, count, A, b, x, v, ws, ws_bytes, d_info, nullptr, stream);
+            if (rc == 0 && (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                            hipEventElapsedTime(&t, e0, e1) != hipSuccess))
+                rc = MDLS_EHIP;
+        }
+        if (rc != 0) break;
+        if (ms) ms[v] = t;
+        if (best < 0 || t < best_ms) {
+            best = v;
+            best_ms = t;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    return rc != 0 ? rc : best;
+}
+
+int mdls_wall_clock_khz(int *khz)
+{
+    int dev = 0;
+    if (!khz) return -1;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess)
+        return MDLS_EHIP;
+    return 0;
 }
 
 int mdls_timing_enable(int on)

@@ -174,7 +174,7 @@ __device__ __forceinline__ int slot_scatter_index(int lane)
 // v = u / u1 (scale rho = gamma/u1), beta = tau u1^2, and column j of T follows from
 // T(0:j, j) = -beta_j T(0:j, 0:j) (Y(:, 0:j)^T v_j) (Schreiber and Van Loan's compact WY).
 template <int P, int W, int R, int NT>
-__global__ __launch_bounds__(NT) void k_panel(PanelArgs g)
+__device__ __forceinline__ void panel_run(const PanelArgs &g, int bid)
 {
     constexpr int S = NT / W;
     constexpr int NW = NT / 64;
@@ -202,7 +202,7 @@ __global__ __launch_bounds__(NT) void k_panel(PanelArgs g)
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int c = tid % W, slot = tid / W;
     const long rstride = (long)g.G * S;
-    const long rbase = (long)blockIdx.x * S + slot;
+    const long rbase = (long)bid * S + slot;
     const int src0 = lane & ~(W - 1);
     const int off = g.off;
     const long hh = (long)g.h + off;
@@ -304,7 +304,7 @@ __global__ __launch_bounds__(NT) void k_panel(PanelArgs g)
                 for (int m = WW; m < 64; m <<= 1) acc_add_acc(t, shfl_xor_acc(t, m));
                 if (g.G > 1) {
                     if (sub == 0) {
-                        double *mine = g.gpart + (size_t)((nbar & 1) * g.G + blockIdx.x) * SLOT;
+                        double *mine = g.gpart + (size_t)((nbar & 1) * g.G + bid) * SLOT;
 #pragma unroll
                         for (int k = 0; k < P; ++k) st_coherent(mine + q * P + k, t.s[k]);
                     }
@@ -393,7 +393,7 @@ __global__ __launch_bounds__(NT) void k_panel(PanelArgs g)
 #pragma unroll
             for (int k = 0; k < P; ++k) s_part[(wid * W + lane) * P + k] = acc.s[k];
         }
-        if (blockIdx.x == 0 && slot == dj) lds_st(&s_head[c * P], a[0]);
+        if (bid == 0 && slot == dj) lds_st(&s_head[c * P], a[0]);
         __syncthreads();  // B1
         if (wid == 0) {
             Acc<P> ta = acc_zero<P>();
@@ -405,13 +405,13 @@ __global__ __launch_bounds__(NT) void k_panel(PanelArgs g)
             }
 #pragma unroll
             for (int m = W; m < (NW * W < 64 ? NW * W : 64); m <<= 1) acc_add_acc(ta, shfl_xor_acc(ta, m));
-            V<P> hd = (blockIdx.x == 0) ? lds_ld<P>(&s_head[(lane % W) * P]) : zero<P>();
+            V<P> hd = (bid == 0) ? lds_ld<P>(&s_head[(lane % W) * P]) : zero<P>();
             if (g.G > 1) {
-                double *mine = g.gpart + (size_t)((nbar & 1) * g.G + blockIdx.x) * SLOT;
+                double *mine = g.gpart + (size_t)((nbar & 1) * g.G + bid) * SLOT;
                 if (lane < W) {
 #pragma unroll
                     for (int k = 0; k < P; ++k) st_coherent(mine + lane * P + k, ta.s[k]);
-                    if (blockIdx.x == 0) {
+                    if (bid == 0) {
 #pragma unroll
                         for (int k = 0; k < P; ++k) st_coherent(mine + (W + lane) * P + k, hd.x[k]);
                     }
@@ -441,7 +441,7 @@ __global__ __launch_bounds__(NT) void k_panel(PanelArgs g)
                 lds_st(&s_gram[(j * W + lane) * P], tot);
                 lds_st(&s_hrow[(j * W + lane) * P], hd);
             }
-        } else if (blockIdx.x == 0 && j > 0) {
+        } else if (bid == 0 && j > 0) {
             if (wid == 2) t_beta(j - 1);
             if (wid == 3) cx = t_g(j - 1);
         }
@@ -475,7 +475,7 @@ __global__ __launch_bounds__(NT) void k_panel(PanelArgs g)
             }
         } else if (wid == 2) {
             if (!zs && pos) cx = recip(sig);
-        } else if (wid == 3 && blockIdx.x == 0 && j > 0) {
+        } else if (wid == 3 && bid == 0 && j > 0) {
             cx = t_w(j - 1, cx);
         }
         __syncthreads();  // M
@@ -509,7 +509,7 @@ __global__ __launch_bounds__(NT) void k_panel(PanelArgs g)
                 rho = pos ? neg(mul(add(x1, mu), cx)) : neg(recip(sub(mu, x1)));
             }
             if (lane == 0) lds_st(&s_rho[j * P], rho);
-        } else if (wid == 3 && blockIdx.x == 0 && j > 0) {
+        } else if (wid == 3 && bid == 0 && j > 0) {
             t_store(j - 1, cx);
         }
         __syncthreads();  // Tb
@@ -533,7 +533,7 @@ __global__ __launch_bounds__(NT) void k_panel(PanelArgs g)
     __syncthreads();
     // ---- 4. the last column's beta and T column; the deferred row updates; v = x rho below
     //         the diagonal; store the panel (rows from the previous diagonal)
-    if (blockIdx.x == 0 && g.wact > 0) {
+    if (bid == 0 && g.wact > 0) {
         if (wid == 2) t_beta(g.wact - 1);
         if (wid == 3) cx = t_w(g.wact - 1, t_g(g.wact - 1));
     }
@@ -553,11 +553,18 @@ __global__ __launch_bounds__(NT) void k_panel(PanelArgs g)
         }
     }
     __syncthreads();
-    if (blockIdx.x == 0 && wid == 3) {
+    if (bid == 0 && wid == 3) {
         if (g.wact > 0) t_store(g.wact - 1, cx);
         for (int jj = g.wact; jj < W; ++jj)
             if (lane < W) stm(g.T, g.tps, (long)jj * W + lane, zero<P>());
     }
+}
+
+// One panel launch: workgroup b runs panel_run(g, b).
+template <int P, int W, int R, int NT>
+__global__ __launch_bounds__(NT) void k_panel(PanelArgs g)
+{
+    panel_run<P, W, R, NT>(g, blockIdx.x);
 }
 
 // ============================================================================ trailing update
@@ -768,6 +775,165 @@ __global__ __launch_bounds__(kThreads) void k_apply_u(ApplyArgs g)
                     acc_fma(t, y, nU[i]);
                 }
                 stm(col, cps, gr, acc_get(t));
+            }
+        }
+    }
+}
+
+// ============================================================================ batched solves
+// Many independent least-squares problems (m <= kBatchRows) in one persistent launch.  Each
+// workgroup takes the next problem from a counter (the plan lists the problems largest
+// m n^2 first, so the longest start first) and solves it alone: narrow Householder panels
+// (panel_run with one workgroup), the update of the columns right of the panel and of b by
+// the workgroup's waves (one column per wave), then the back substitution of R x = (Q^T b)
+// with the reciprocals of R's diagonal formed in parallel.  Start and end times (wall clock
+// ticks) are recorded per problem.
+constexpr int kBatchRows = 512;
+
+struct BatchDesc {
+    int m, n;
+    long long a_off, b_off, x_off;  // doubles from the A, b, x base pointers
+    int idx, pad;                   // position of the problem in the caller's list
+};
+
+struct BatchArgs {
+    const BatchDesc *desc;  // in processing order
+    int count;
+    double *A, *b, *x;
+    double *scratch;    // per workgroup: T (W*W*P) and beta (kBatchRows*P)
+    unsigned *counter;  // zero on entry
+    int *info;          // per problem
+    long long *times;   // per problem: start, end; or null
+};
+
+// C := C - Y T^T (Y^T C) for the ncols columns at C0 (plane stride ps, ld lda) and the column
+// b0 (plane stride bps), h rows from the panel's diagonal; one column per wave.
+template <int P, int W, int NT>
+__device__ __forceinline__ void batch_update(const double *Y, long lda, long ps, int h, int wact, const double *T,
+                                             double *C0, int ncols, double *b0, long bps)
+{
+    constexpr int NW = NT / 64, LPI = 64 / W, NQ = (W * W + 63) / 64;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int col = wid; col <= ncols; col += NW) {
+        double *cp = (col < ncols) ? C0 + (long)col * lda : b0;
+        const long cps = (col < ncols) ? ps : bps;
+        Acc<P> s[W];
+#pragma unroll
+        for (int i = 0; i < W; ++i) s[i] = acc_zero<P>();
+        int nt = 0;
+        for (int r = lane; r < h; r += 64) {
+            const V<P> cv = ldm<P>(cp, cps, r);
+#pragma unroll
+            for (int i = 0; i < W; ++i) acc_fma_step(s[i], y_entry<P>(Y, lda, ps, r, i, h, wact), cv, nt);
+            ++nt;
+        }
+        reduce_scatter<P, W>(s, lane);
+        const V<P> S = acc_get(s[0]);  // lane q: S_(q / LPI)
+        // -U_i = -sum_{l <= i} T(l, i) S_l: lane q = i W + l (+ 64 k) forms one product
+        const int l = lane % W;
+        const V<P> sl = shfl_md(S, l * LPI);
+        V<P> un[NQ];
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) {
+            const int i = (lane + 64 * k) / W;
+            Acc<P> u = acc_zero<P>();
+            if (l <= i && i < wact) acc_fma(u, ldm<P>(T, (long)W * W, (long)i * W + l), sl);
+#pragma unroll
+            for (int m = 1; m < W; m <<= 1) acc_add_acc(u, shfl_xor_acc(u, m));
+            un[k] = neg(acc_get(u));
+        }
+        V<P> nU[W];
+#pragma unroll
+        for (int i = 0; i < W; ++i) nU[i] = shfl_md(un[(i * W) / 64], (i * W) % 64);
+        for (int r = lane; r < h; r += 64) {
+            Acc<P> t = acc_from(ldm<P>(cp, cps, r));
+#pragma unroll
+            for (int i = 0; i < W; ++i) acc_fma(t, y_entry<P>(Y, lda, ps, r, i, h, wact), nU[i]);
+            stm(cp, cps, r, acc_get(t));
+        }
+    }
+}
+
+// x = R^-1 y for the n x n upper triangle of A and y = b(0:n) (Algorithm 1 with one tile,
+// column-oriented): x_i = y_i / R_ii, then y_t -= R_ti x_i for t < i.  Returns the 1-based
+// index of the first exactly-zero diagonal element, or 0.
+template <int P, int NT>
+__device__ __forceinline__ int batch_backsub(const double *A, long lda, long ps, int n, const double *b, long bps,
+                                             double *x, long xps, double *s_y, double *s_r, int *s_zero)
+{
+    const int tid = threadIdx.x;
+    if (tid == 0) *s_zero = INT_MAX;
+    __syncthreads();
+    for (int i = tid; i < n; i += NT) {
+        const V<P> d = ldm<P>(A, ps, (long)i * lda + i);
+        const bool z = is_zero(d);
+        if (z) atomicMin(s_zero, i);
+        lds_st(&s_r[i * P], z ? zero<P>() : recip(d));
+        lds_st(&s_y[i * P], ldm<P>(b, bps, i));
+    }
+    __syncthreads();
+    const int zi = *s_zero;
+    for (int i = n - 1; i >= 0; --i) {
+        const V<P> xi = mul(lds_ld<P>(&s_y[i * P]), lds_ld<P>(&s_r[i * P]));
+        if (tid == 0) stm(x, xps, i, xi);
+        for (int t = tid; t < i; t += NT)
+            lds_st(&s_y[t * P], fma(lds_ld<P>(&s_y[t * P]), neg(ldm<P>(A, ps, (long)i * lda + t)), xi));
+        __syncthreads();
+    }
+    return zi == INT_MAX ? 0 : zi + 1;
+}
+
+template <int P, int W, int R, int NT>
+__global__ __launch_bounds__(NT) void k_batch(BatchArgs g)
+{
+    static_assert((NT / W) * R >= kBatchRows, "k_batch: a panel must hold kBatchRows rows");
+    __shared__ double s_y[kBatchRows * P];
+    __shared__ double s_r[kBatchRows * P];
+    __shared__ int s_next, s_zero;
+    constexpr long WWP = (long)W * W * P;
+    double *T = g.scratch + (long)blockIdx.x * (WWP + (long)kBatchRows * P);
+    double *beta = T + WWP;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_next = (int)atomicAdd(g.counter, 1u);
+        __syncthreads();
+        const int q = s_next;
+        if (q >= g.count) break;  // every workgroup leaves once the list is exhausted
+        const long long t0 = wall_clock64();
+        const BatchDesc d = g.desc[q];
+        double *A = g.A + d.a_off;
+        double *bp = g.b + d.b_off;
+        const long lda = d.m, ps = (long)d.m * d.n;
+        for (int c0 = 0; c0 < d.n; c0 += W) {
+            PanelArgs pa;
+            pa.A = A + (long)c0 * lda + c0;
+            pa.lda = lda;
+            pa.ps = ps;
+            pa.h = d.m - c0;
+            pa.wact = (d.n - c0 < W) ? (d.n - c0) : W;
+            pa.off = 0;
+            pa.Yp = nullptr;
+            pa.Tp = nullptr;
+            pa.beta = beta + c0;
+            pa.bps = kBatchRows;
+            pa.T = T;
+            pa.tps = (long)W * W;
+            pa.gpart = nullptr;
+            pa.gbar = nullptr;
+            pa.err = nullptr;
+            pa.G = 1;
+            panel_run<P, W, R, NT>(pa, 0);
+            __syncthreads();
+            batch_update<P, W, NT>(pa.A, lda, ps, pa.h, pa.wact, T, A + (long)(c0 + pa.wact) * lda + c0,
+                                   d.n - c0 - pa.wact, bp + c0, d.m);
+            __syncthreads();
+        }
+        const int inf = batch_backsub<P, NT>(A, lda, ps, d.n, bp, d.m, g.x + d.x_off, d.n, s_y, s_r, &s_zero);
+        if (threadIdx.x == 0) {
+            g.info[d.idx] = inf;
+            if (g.times) {
+                g.times[2L * d.idx] = t0;
+                g.times[2L * d.idx + 1] = wall_clock64();
             }
         }
     }
@@ -1420,6 +1586,87 @@ int backsub_t(int n, int tile, const double *R, int ldr, double *x, void *ws, in
     backsub_tiles<P>(cx, n, tile, R, ldr, (long)ldr * n, x, n, d_info);
     return hipGetLastError() == hipSuccess ? 0 : MDLS_EHIP;
 }
+
+// ---------------------------------------------------------------- batched solves (host)
+// Kernel variants (threads, panel width, rows per thread) tried by the autotuner; each holds
+// kBatchRows rows per panel.
+constexpr int kBatchVariants = 3;
+constexpr int kBatchWMax = 16;
+
+inline int batch_variants(int P) { return (P == 2 || P == 4) ? kBatchVariants : 0; }
+
+struct BatchLayout {
+    size_t plan, ctr, scratch, total;
+    int maxgrid;
+};
+
+inline BatchLayout batch_layout(int P, int count)
+{
+    BatchLayout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off += align256(bytes);
+        return at;
+    };
+    L.maxgrid = 8 * kCUs;
+    L.plan = take(sizeof(BatchDesc) * (size_t)(count > 0 ? count : 1));
+    L.ctr = take(sizeof(unsigned) * 64);
+    L.scratch = take(sizeof(double) * (size_t)L.maxgrid * ((size_t)kBatchWMax * kBatchWMax * P + (size_t)kBatchRows * P));
+    L.total = off;
+    return L;
+}
+
+template <int P, int W, int R, int NT>
+int launch_batch(BatchArgs a, int maxgrid, hipStream_t s)
+{
+    int per_cu = 0, cus = 0, dev = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<P, W, R, NT>, NT, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                                hipSuccess || cus < 1)
+        cus = kCUs;
+    int grid = per_cu * cus;
+    if (grid > maxgrid) grid = maxgrid;
+    if (grid > a.count) grid = a.count;
+    MDLS_LAUNCH("k_zero", P, 0, k_zero_u32, dim3(1), dim3(64), s, a.counter, 1);
+    MDLS_LAUNCH("k_batch", P, 0, (k_batch<P, W, R, NT>), dim3(grid), dim3(NT), s, a);
+    return hipGetLastError() == hipSuccess ? 0 : MDLS_EHIP;
+}
+
+template <int P>
+int batch_solve_t(int count, double *A, double *b, double *x, int variant, void *ws, int *d_info, long long *d_times,
+                  hipStream_t s)
+{
+    const BatchLayout L = batch_layout(P, count);
+    BatchArgs a;
+    a.desc = (const BatchDesc *)((char *)ws + L.plan);
+    a.count = count;
+    a.A = A;
+    a.b = b;
+    a.x = x;
+    a.scratch = (double *)((char *)ws + L.scratch);
+    a.counter = (unsigned *)((char *)ws + L.ctr);
+    a.info = d_info;
+    a.times = d_times;
+    if constexpr (P == 2) {
+        switch (variant) {
+        case 0: return launch_batch<2, 8, 16, 256>(a, L.maxgrid, s);
+        case 1: return launch_batch<2, 8, 8, 512>(a, L.maxgrid, s);
+        case 2: return launch_batch<2, 4, 8, 256>(a, L.maxgrid, s);
+        }
+    } else if constexpr (P == 4) {
+        switch (variant) {
+        case 0: return launch_batch<4, 4, 8, 256>(a, L.maxgrid, s);
+        case 1: return launch_batch<4, 4, 4, 512>(a, L.maxgrid, s);
+        case 2: return launch_batch<4, 8, 16, 256>(a, L.maxgrid, s);
+        }
+    }
+    return MDLS_EUNSUPPORTED;
+}
+
+#define MDLS_BATCH_FOR_PRECISION(X, P) \
+    X template int batch_solve_t<P>(int, double *, double *, double *, int, void *, int *, long long *, hipStream_t);
 
 #define MDLS_FOR_PRECISION(X, P)                                                                        \
     X template int solve_t<P>(int, int, int, double *, int, double *, double *, void *, int *, hipStream_t);     \

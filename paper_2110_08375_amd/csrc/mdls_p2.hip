@@ -3,4 +3,5 @@
 
 namespace mdls_impl {
 MDLS_FOR_PRECISION(, 2)
+MDLS_BATCH_FOR_PRECISION(, 2)
 }  // namespace mdls_impl

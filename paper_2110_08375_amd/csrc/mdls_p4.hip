@@ -3,4 +3,5 @@
 
 namespace mdls_impl {
 MDLS_FOR_PRECISION(, 4)
+MDLS_BATCH_FOR_PRECISION(, 4)
 }  // namespace mdls_impl

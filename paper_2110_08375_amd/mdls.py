@@ -20,7 +20,14 @@ MDLS_EHIP, MDLS_EUNSUPPORTED = -100, -101
 # every symbol include/mdls.h declares
 EXPORTS = ("mdls_max_rows", "mdls_workspace_bytes", "mdls_qr", "mdls_apply_qt", "mdls_form_w",
            "mdls_backsub", "mdls_solve", "mdls_status_string", "mdls_timing_enable", "mdls_timing_reset",
-           "mdls_timing_query", "mdls_timing_kernels")
+           "mdls_timing_query", "mdls_timing_kernels", "mdls_batch_workspace_bytes", "mdls_batch_plan",
+           "mdls_solve_batched", "mdls_batch_variants", "mdls_batch_autotune", "mdls_wall_clock_khz")
+
+
+class BatchDesc(ctypes.Structure):
+    """mdls_batch_desc: problem shape and offsets (in doubles) into the A, b, x pools."""
+    _fields_ = [("m", ctypes.c_int), ("n", ctypes.c_int), ("a_off", ctypes.c_longlong),
+                ("b_off", ctypes.c_longlong), ("x_off", ctypes.c_longlong)]
 
 _lib = None
 
@@ -54,8 +61,17 @@ def lib():
         L.mdls_timing_query.argtypes = [ctypes.c_char_p, i, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_long), ctypes.POINTER(ctypes.c_double)]
         L.mdls_timing_kernels.argtypes = [ctypes.c_char_p, i]
+        L.mdls_batch_workspace_bytes.argtypes = [i, i]
+        L.mdls_batch_workspace_bytes.restype = sz
+        L.mdls_batch_plan.argtypes = [i, i, ctypes.POINTER(BatchDesc), vp, sz, vp]
+        L.mdls_solve_batched.argtypes = [i, i, vp, vp, vp, i, vp, sz, vp, vp, vp]
+        L.mdls_batch_variants.argtypes = [i]
+        L.mdls_batch_autotune.argtypes = [i, i, vp, vp, sz, sz, vp, vp, vp, vp, sz, vp, ctypes.POINTER(ctypes.c_float),
+                                          vp]
+        L.mdls_wall_clock_khz.argtypes = [ctypes.POINTER(ctypes.c_int)]
         for f in ("mdls_qr", "mdls_apply_qt", "mdls_form_w", "mdls_backsub", "mdls_solve", "mdls_timing_enable",
-                  "mdls_timing_reset", "mdls_timing_query", "mdls_timing_kernels"):
+                  "mdls_timing_reset", "mdls_timing_query", "mdls_timing_kernels", "mdls_batch_plan",
+                  "mdls_solve_batched", "mdls_batch_variants", "mdls_batch_autotune", "mdls_wall_clock_khz"):
             getattr(L, f).restype = i
         _lib = L
     return _lib
@@ -209,3 +225,58 @@ def timing_query(name: str = "", p: int = 0):
     _check(lib().mdls_timing_query(name.encode(), p, ctypes.byref(ms), ctypes.byref(cnt), ctypes.byref(work)),
            "mdls_timing_query")
     return ms.value, cnt.value, work.value
+
+
+# ----------------------------------------------------------------------------- batched solves
+def batch_descs(p: int, shapes):
+    """Descriptors for problems packed back to back: A pool (P planes of m x n each), b pool
+    (P planes of m), x pool (P planes of n).  Returns (descs, a_len, b_len, x_len)."""
+    descs = (BatchDesc * len(shapes))()
+    a = b = x = 0
+    for k, (m, n) in enumerate(shapes):
+        descs[k] = BatchDesc(int(m), int(n), a, b, x)
+        a += p * m * n
+        b += p * m
+        x += p * n
+    return descs, a, b, x
+
+
+def batch_workspace(p: int, count: int, device="cuda"):
+    import torch
+
+    nb = lib().mdls_batch_workspace_bytes(p, count)
+    if nb == 0:
+        raise ValueError("invalid precision or count for a batch workspace")
+    return torch.empty(nb, dtype=torch.uint8, device=device)
+
+
+def batch_plan(p: int, descs, ws):
+    _check(lib().mdls_batch_plan(p, len(descs), descs, _ptr(ws), ws.numel(), _stream()), "mdls_batch_plan")
+
+
+def batch_variants(p: int) -> int:
+    return lib().mdls_batch_variants(p)
+
+
+def solve_batched(p: int, count: int, A, b, x, variant: int, ws, info, times=None):
+    """Solve the planned batch in one persistent launch on the current stream."""
+    _check(lib().mdls_solve_batched(p, count, _ptr(A), _ptr(b), _ptr(x), variant, _ptr(ws), ws.numel(), _ptr(info),
+                                    _ptr(times), _stream()), "mdls_solve_batched")
+    return x, info
+
+
+def batch_autotune(p: int, count: int, A_src, b_src, A, b, x, ws, info):
+    """Time every kernel variant on copies of the batch; returns (best variant, ms per variant)."""
+    nv = batch_variants(p)
+    ms = (ctypes.c_float * max(nv, 1))()
+    rc = lib().mdls_batch_autotune(p, count, _ptr(A_src), _ptr(b_src), A_src.numel(), b_src.numel(), _ptr(A), _ptr(b),
+                                   _ptr(x), _ptr(ws), ws.numel(), _ptr(info), ms, _stream())
+    if rc < 0:
+        _check(rc, "mdls_batch_autotune")
+    return rc, [ms[i] for i in range(nv)]
+
+
+def wall_clock_khz() -> int:
+    k = ctypes.c_int(0)
+    _check(lib().mdls_wall_clock_khz(ctypes.byref(k)), "mdls_wall_clock_khz")
+    return k.value

@@ -89,3 +89,30 @@ def test_binding_refuses_cpu_tensors(L):
     b = torch.zeros((2, 8), dtype=torch.float64)
     with pytest.raises(ValueError):
         M.solve(2, A, b, 4)
+
+
+def test_batched_entry_point_errors(L):
+    from paper_2110_08375_amd import mdls
+
+    vp = ctypes.c_void_p
+    d = vp(16)
+    assert L.mdls_batch_variants(2) >= 1 and L.mdls_batch_variants(4) >= 1
+    assert L.mdls_batch_variants(8) == 0 and L.mdls_batch_variants(3) == 0
+    assert L.mdls_batch_workspace_bytes(2, 512) > 0
+    assert L.mdls_batch_workspace_bytes(8, 512) == 0 and L.mdls_batch_workspace_bytes(2, 0) == 0
+    ws = L.mdls_batch_workspace_bytes(2, 3)
+    good, _, _, _ = mdls.batch_descs(2, [(40, 20), (512, 512), (16, 1)])
+    for bad in ([(10, 20), (40, 20), (16, 1)], [(513, 20), (40, 20), (16, 1)], [(40, 0), (40, 20), (16, 1)]):
+        descs, _, _, _ = mdls.batch_descs(2, bad)
+        assert L.mdls_batch_plan(2, 3, descs, d, ws, None) == -3
+    assert L.mdls_batch_plan(8, 3, good, d, ws, None) == -1
+    assert L.mdls_batch_plan(2, 0, good, d, ws, None) == -2
+    assert L.mdls_batch_plan(2, 3, None, d, ws, None) == -3
+    assert L.mdls_batch_plan(2, 3, good, None, ws, None) == -4
+    assert L.mdls_batch_plan(2, 3, good, d, ws - 1, None) == -5
+    sb = L.mdls_solve_batched
+    assert sb(2, 3, d, d, d, L.mdls_batch_variants(2), d, ws, d, None, None) == -6
+    assert sb(2, 3, d, d, d, -1, d, ws, d, None, None) == -6
+    assert sb(2, 3, None, d, d, 0, d, ws, d, None, None) == -3
+    assert sb(2, 3, d, d, d, 0, d, ws, None, None, None) == -9
+    assert sb(4, 3, d, d, d, 0, d, L.mdls_batch_workspace_bytes(4, 3) - 1, d, None, None) == -8
