@@ -12,7 +12,9 @@ three solves (Table 1 weights, see paper_2110_08375_amd/opcount.py) divided by t
 of the step, in TFLOP/s.  The JSON line also carries, per precision, the solve time and its
 fraction of the FP64 peak; a roofline entry for the kernel that takes the most device time
 (per-kernel HIP-event timing inside the library, on the solve's stream); and the CPU oracle
-timed on a bounded sample of the same workload.
+timed on a bounded sample of the same workload; and the batched form (512 uneven dd and qd
+problems in one persistent launch: solves/s, p50/p99 per-problem latency) against the plain
+solver called once per problem.
 """
 from __future__ import annotations
 
@@ -90,6 +92,78 @@ def cpu_baseline(sample, threads):
     return total_ops / total_s / 1e12, total_s
 
 
+def batched_run(M, P, count, seed, dev, reps, per_problem):
+    """The batched workload: count problems, m uniform in [32, 512], n uniform in [16, m], entries as
+    the n = 1024 problem; one persistent launch (autotuned variant) against the plain solver called
+    once per problem."""
+    import numpy as np
+    import torch
+
+    import mdgen
+    from paper_2110_08375_amd import opcount
+
+    shapes = mdgen.batch_shapes(count, seed)
+    descs, a_len, b_len, x_len = M.batch_descs(P, shapes)
+    A = np.empty(a_len)
+    b = np.empty(b_len)
+    for k, (m, n) in enumerate(shapes):
+        A[descs[k].a_off:descs[k].a_off + P * m * n] = mdgen.md_uniform(P, m, n, seed + k, mdgen.STREAM_A).ravel()
+        b[descs[k].b_off:descs[k].b_off + P * m] = mdgen.md_vector(P, m, seed + k, mdgen.STREAM_B).ravel()
+    A0 = torch.from_numpy(A).to(dev)
+    b0 = torch.from_numpy(b).to(dev)
+    Aw, bw = torch.empty_like(A0), torch.empty_like(b0)
+    x = torch.zeros(x_len, dtype=torch.float64, device=dev)
+    info = torch.zeros(count, dtype=torch.int32, device=dev)
+    times = torch.zeros(2 * count, dtype=torch.int64, device=dev)
+    ws = M.batch_workspace(P, count, dev)
+    M.batch_plan(P, descs, ws)
+    best, tune_ms = M.batch_autotune(P, count, A0, b0, Aw, bw, x, ws, info)
+    ms = []
+    for _ in range(reps):
+        Aw.copy_(A0)
+        bw.copy_(b0)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        M.solve_batched(P, count, Aw, bw, x, best, ws, info, times)
+        e1.record()
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    if int((info != 0).sum().item()) != 0:
+        raise RuntimeError("batched solve reported a zero pivot")
+    t = times.cpu().numpy().reshape(-1, 2)
+    lat = (t[:, 1] - t[:, 0]) / M.wall_clock_khz()  # ms
+    ops = sum(opcount.ls_double_ops(P, m, n) for m, n in shapes)
+    ms_b = float(np.median(ms))
+    out = {"variant": best, "autotune_ms": [round(v, 3) for v in tune_ms], "ms": round(ms_b, 3),
+           "solves_per_s": round(count / (ms_b * 1e-3), 1), "tflops": round(ops / (ms_b * 1e-3) / 1e12, 4),
+           "p50_ms": round(float(np.percentile(lat, 50)), 4), "p99_ms": round(float(np.percentile(lat, 99)), 4),
+           "max_ms": round(float(lat.max()), 4)}
+    log("batched %s: variant %d, %.3f ms for %d problems (%.1f solves/s), p50 %.3f ms p99 %.3f ms"
+        % (PNAME[P], best, ms_b, count, out["solves_per_s"], out["p50_ms"], out["p99_ms"]))
+    if per_problem:
+        # the plain solver, one call (several launches) per problem, tile = largest divisor of n <= 128
+        xs = [torch.empty((P, n), dtype=torch.float64, device=dev) for _, n in shapes]
+        wss = {}
+        Aw.copy_(A0)
+        bw.copy_(b0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k, (m, n) in enumerate(shapes):
+            tile = max(t for t in range(1, min(n, 128) + 1) if n % t == 0)
+            Ak = Aw[descs[k].a_off:descs[k].a_off + P * m * n].view(P, n, m)
+            bk = bw[descs[k].b_off:descs[k].b_off + P * m].view(P, m)
+            key = (m, n, tile)
+            if key not in wss:
+                wss[key] = M.workspace(P, m, n, tile, dev)
+            M.solve(P, Ak, bk, tile, x=xs[k], ws=wss[key], info=info[k:k + 1])
+        torch.cuda.synchronize()
+        ms_p = (time.perf_counter() - t0) * 1e3
+        out["per_problem_launches"] = {"ms": round(ms_p, 3), "solves_per_s": round(count / (ms_p * 1e-3), 1)}
+        out["speedup_vs_per_problem"] = round(ms_p / ms_b, 2)
+        log("per-problem launches %s: %.3f ms (%.1f solves/s)" % (PNAME[P], ms_p, count / (ms_p * 1e-3)))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,6 +175,8 @@ def main():
     ap.add_argument("--precisions", default="2,4,8", help="limb counts, e.g. 2,4,8")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-solves measurement")
+    ap.add_argument("--batch", type=int, default=512)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -215,6 +291,14 @@ def main():
                                          "frac": round(tach / peak, 5), "avg_launch_us": round(tms * 1e3 / tcnt, 3)}
         log("dominant kernel %s: %.3f ms over %d launches, %.3f TFLOP/s" % (label, ms, cnt, achieved))
 
+    batched = None
+    if not args.no_batched:
+        batched = {"workload": "%d independent least-squares problems, m uniform in [32, 512], n uniform in "
+                               "[16, m], entries as the n = 1024 problem, one persistent launch (autotuned "
+                               "variant) vs the plain solver called per problem" % args.batch}
+        for P in (2, 4):
+            batched[PNAME[P]] = batched_run(M, P, args.batch, 4000 + P, dev, 3, True)
+
     cpu = None
     if not args.no_cpu_baseline:
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -243,6 +327,7 @@ def main():
         "per_precision": per_prec,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "batched": batched,
     }
     print(json.dumps(out), flush=True)
 

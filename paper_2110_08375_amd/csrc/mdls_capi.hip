@@ -266,15 +266,17 @@ int mdls_batch_plan(int p, int count, const mdls_batch_desc *h_desc, void *ws, s
     for (int i = 0; i < count; ++i) {
         const mdls_batch_desc &d = h_desc[i];
         if (d.n < 1 || d.m < d.n || d.m > kBatchRows || d.a_off < 0 || d.b_off < 0 || d.x_off < 0) return -3;
-        plan[(size_t)i] = BatchDesc{d.m, d.n, d.a_off, d.b_off, d.x_off, i, 0};
+        plan[(size_t)i] = BatchDesc{d.m, d.n, d.a_off, d.b_off, d.x_off, i, 1};
     }
-    // longest processing time first: the largest m n^2 start first
-    std::stable_sort(plan.begin(), plan.end(), [](const BatchDesc &x, const BatchDesc &y) {
-        return (double)x.m * x.n * x.n > (double)y.m * y.n * y.n;
-    });
+    const std::vector<int> slots = batch_schedule(plan);
+    const int nslots = (int)slots.size();
     const BatchLayout L = batch_layout(p, count);
-    if (hipMemcpyAsync((char *)ws + L.plan, plan.data(), sizeof(BatchDesc) * plan.size(), hipMemcpyHostToDevice,
-                       stream) != hipSuccess)
+    char *w = (char *)ws;
+    if (hipMemcpyAsync(w + L.plan, plan.data(), sizeof(BatchDesc) * plan.size(), hipMemcpyHostToDevice, stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(w + L.slots, slots.data(), sizeof(int) * slots.size(), hipMemcpyHostToDevice, stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(w + L.nslots, &nslots, sizeof(int), hipMemcpyHostToDevice, stream) != hipSuccess)
         return MDLS_EHIP;
     return hipStreamSynchronize(stream) == hipSuccess ? 0 : MDLS_EHIP;
 }

@@ -21,10 +21,12 @@
 //
 // Multiple-double numbers are P limb planes (limb 0 most significant); see md.hpp for the
 // arithmetic.
+#include <algorithm>
 #include <climits>
 #include <cstdint>
 #include <cstdio>
 #include <cstdlib>
+#include <vector>
 
 #pragma once
 #include "mdls.h"
@@ -782,39 +784,51 @@ __global__ __launch_bounds__(kThreads) void k_apply_u(ApplyArgs g)
 
 // ============================================================================ batched solves
 // Many independent least-squares problems (m <= kBatchRows) in one persistent launch.  Each
-// workgroup takes the next problem from a counter (the plan lists the problems largest
-// m n^2 first, so the longest start first) and solves it alone: narrow Householder panels
-// (panel_run with one workgroup), the update of the columns right of the panel and of b by
-// the workgroup's waves (one column per wave), then the back substitution of R x = (Q^T b)
-// with the reciprocals of R's diagonal formed in parallel.  Start and end times (wall clock
-// ticks) are recorded per problem.
+// workgroup takes the next slot from a counter; a slot names a problem and a member index.
+// The plan lists the problems largest m n^2 first and gives the largest a team of T
+// workgroups (T consecutive slots at the head of the list, so every team is resident from
+// the start), the others one.  A team solves its problem with narrow Householder panels
+// (panel_run with T workgroups and the team's own barrier counters and exchange slots), the
+// update of the columns right of the panel and of b split over the team's waves (one column
+// per wave), a team barrier after each step, and member 0 does the back substitution of
+// R x = (Q^T b) with the reciprocals of R's diagonal formed in parallel.  Start and end
+// times (wall clock ticks) are recorded per problem.
 constexpr int kBatchRows = 512;
+constexpr int kTeamMax = 16;      // most workgroups on one problem
+constexpr int kTeamSlots = 128;   // most workgroups in teams (T > 1) per batch
+constexpr int kTeamCtrs = 2 + kBatchRows / 4;  // team barrier + one counter per panel (W >= 4)
 
 struct BatchDesc {
     int m, n;
     long long a_off, b_off, x_off;  // doubles from the A, b, x base pointers
-    int idx, pad;                   // position of the problem in the caller's list
+    int idx;                        // position of the problem in the caller's list
+    int team;                       // workgroups on this problem
 };
 
 struct BatchArgs {
     const BatchDesc *desc;  // in processing order
-    int count;
+    const int *slots;       // per slot: index into desc * kTeamMax + member
+    const int *nslots;      // number of slots (device)
     double *A, *b, *x;
-    double *scratch;    // per workgroup: T (W*W*P) and beta (kBatchRows*P)
+    double *scratch;    // per workgroup: beta (kBatchRows*P)
     unsigned *counter;  // zero on entry
+    unsigned *tctr;     // per problem: kTeamCtrs barrier counters, zero on entry
+    double *xch;        // per problem: T (W^2 P) and panel_run's exchange slots (2 kTeamMax (W^2 + 2W) P)
+    int *err;           // set if a team barrier times out
     int *info;          // per problem
     long long *times;   // per problem: start, end; or null
 };
 
 // C := C - Y T^T (Y^T C) for the ncols columns at C0 (plane stride ps, ld lda) and the column
-// b0 (plane stride bps), h rows from the panel's diagonal; one column per wave.
+// b0 (plane stride bps, index ncols), h rows from the panel's diagonal; one column per wave,
+// columns first, first + step, ... for this wave.
 template <int P, int W, int NT>
 __device__ __forceinline__ void batch_update(const double *Y, long lda, long ps, int h, int wact, const double *T,
-                                             double *C0, int ncols, double *b0, long bps)
+                                             double *C0, int ncols, double *b0, long bps, int first, int step)
 {
-    constexpr int NW = NT / 64, LPI = 64 / W, NQ = (W * W + 63) / 64;
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    for (int col = wid; col <= ncols; col += NW) {
+    constexpr int LPI = 64 / W, NQ = (W * W + 63) / 64;
+    const int lane = threadIdx.x & 63;
+    for (int col = first; col <= ncols; col += step) {
         double *cp = (col < ncols) ? C0 + (long)col * lda : b0;
         const long cps = (col < ncols) ? ps : bps;
         Acc<P> s[W];
@@ -887,22 +901,39 @@ template <int P, int W, int R, int NT>
 __global__ __launch_bounds__(NT) void k_batch(BatchArgs g)
 {
     static_assert((NT / W) * R >= kBatchRows, "k_batch: a panel must hold kBatchRows rows");
+    constexpr int NW = NT / 64;
+    constexpr long WWP = (long)W * W * P;
+    constexpr long XCHP = WWP + 2L * kTeamMax * (W * W + 2 * W) * P;
     __shared__ double s_y[kBatchRows * P];
     __shared__ double s_r[kBatchRows * P];
     __shared__ int s_next, s_zero;
-    constexpr long WWP = (long)W * W * P;
-    double *T = g.scratch + (long)blockIdx.x * (WWP + (long)kBatchRows * P);
-    double *beta = T + WWP;
+    const int wid = threadIdx.x >> 6;
+    double *beta = g.scratch + (long)blockIdx.x * kBatchRows * P;
+    const int nslots = *g.nslots;
     for (;;) {
         __syncthreads();
         if (threadIdx.x == 0) s_next = (int)atomicAdd(g.counter, 1u);
         __syncthreads();
-        const int q = s_next;
-        if (q >= g.count) break;  // every workgroup leaves once the list is exhausted
+        const int slot = s_next;
+        if (slot >= nslots) break;  // every workgroup leaves once the list is exhausted
         const long long t0 = wall_clock64();
+        const int q = g.slots[slot] / kTeamMax, mem = g.slots[slot] % kTeamMax;
         const BatchDesc d = g.desc[q];
+        const int team = d.team;
+        unsigned *ctr = g.tctr + (long)d.idx * kTeamCtrs;
+        unsigned nsync = 0;
+        // all members meet (team > 1); the barrier's fences make every member's stores visible
+        auto team_sync = [&]() __attribute__((always_inline)) {
+            if (team > 1) {
+                __syncthreads();
+                ++nsync;
+                if (wid == 0) grid_sync(ctr, nsync * (unsigned)team, g.err);
+                __syncthreads();
+            }
+        };
         double *A = g.A + d.a_off;
         double *bp = g.b + d.b_off;
+        double *pxch = g.xch + (long)d.idx * XCHP;
         const long lda = d.m, ps = (long)d.m * d.n;
         for (int c0 = 0; c0 < d.n; c0 += W) {
             PanelArgs pa;
@@ -916,24 +947,28 @@ __global__ __launch_bounds__(NT) void k_batch(BatchArgs g)
             pa.Tp = nullptr;
             pa.beta = beta + c0;
             pa.bps = kBatchRows;
-            pa.T = T;
+            pa.T = pxch;  // written by member 0, read by every member after the team barrier
             pa.tps = (long)W * W;
-            pa.gpart = nullptr;
-            pa.gbar = nullptr;
-            pa.err = nullptr;
-            pa.G = 1;
-            panel_run<P, W, R, NT>(pa, 0);
+            pa.gpart = pxch + WWP;
+            pa.gbar = ctr + 1 + c0 / W;
+            pa.err = g.err;
+            pa.G = team;
+            panel_run<P, W, R, NT>(pa, mem);
+            team_sync();
+            batch_update<P, W, NT>(pa.A, lda, ps, pa.h, pa.wact, pa.T, A + (long)(c0 + pa.wact) * lda + c0,
+                                   d.n - c0 - pa.wact, bp + c0, d.m, mem * NW + wid, team * NW);
             __syncthreads();
-            batch_update<P, W, NT>(pa.A, lda, ps, pa.h, pa.wact, T, A + (long)(c0 + pa.wact) * lda + c0,
-                                   d.n - c0 - pa.wact, bp + c0, d.m);
-            __syncthreads();
+            team_sync();
         }
-        const int inf = batch_backsub<P, NT>(A, lda, ps, d.n, bp, d.m, g.x + d.x_off, d.n, s_y, s_r, &s_zero);
-        if (threadIdx.x == 0) {
-            g.info[d.idx] = inf;
-            if (g.times) {
-                g.times[2L * d.idx] = t0;
-                g.times[2L * d.idx + 1] = wall_clock64();
+        if (mem == 0) {
+            const int inf = batch_backsub<P, NT>(A, lda, ps, d.n, bp, d.m, g.x + d.x_off, d.n, s_y, s_r, &s_zero);
+            if (threadIdx.x == 0) {
+                const bool late = team > 1 && __hip_atomic_load(g.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+                g.info[d.idx] = late ? -1 : inf;
+                if (g.times) {
+                    g.times[2L * d.idx] = t0;
+                    g.times[2L * d.idx + 1] = wall_clock64();
+                }
             }
         }
     }
@@ -1596,7 +1631,7 @@ constexpr int kBatchWMax = 16;
 inline int batch_variants(int P) { return (P == 2 || P == 4) ? kBatchVariants : 0; }
 
 struct BatchLayout {
-    size_t plan, ctr, scratch, total;
+    size_t plan, slots, nslots, ctr, tctr, xch, scratch, total;
     int maxgrid;
 };
 
@@ -1609,16 +1644,49 @@ inline BatchLayout batch_layout(int P, int count)
         off += align256(bytes);
         return at;
     };
+    const size_t cnt = (size_t)(count > 0 ? count : 1);
+    const size_t xchp = ((size_t)kBatchWMax * kBatchWMax + 2 * (size_t)kTeamMax * (kBatchWMax * kBatchWMax + 2 * kBatchWMax)) * P;
     L.maxgrid = 8 * kCUs;
-    L.plan = take(sizeof(BatchDesc) * (size_t)(count > 0 ? count : 1));
-    L.ctr = take(sizeof(unsigned) * 64);
-    L.scratch = take(sizeof(double) * (size_t)L.maxgrid * ((size_t)kBatchWMax * kBatchWMax * P + (size_t)kBatchRows * P));
+    L.plan = take(sizeof(BatchDesc) * cnt);
+    L.slots = take(sizeof(int) * cnt * kTeamMax);
+    L.nslots = take(sizeof(int));
+    L.ctr = take(sizeof(unsigned) * 64);  // [0] slot counter, [1] barrier time-out flag
+    L.tctr = take(sizeof(unsigned) * cnt * kTeamCtrs);
+    L.xch = take(sizeof(double) * cnt * xchp);
+    L.scratch = take(sizeof(double) * (size_t)L.maxgrid * kBatchRows * P);
     L.total = off;
     return L;
 }
 
+// Order and teams of a batch: problems largest m n^2 first (longest processing time
+// first); a problem whose work (m n^2 - n^3/3 multiply-adds) is at least twice the average
+// work per resident workgroup (total / 2 kCUs) gets that many workgroups, at most kTeamMax,
+// while at most kTeamSlots workgroups are in teams.  Returns the slot list (problem index
+// in the sorted plan * kTeamMax + member).
+inline std::vector<int> batch_schedule(std::vector<BatchDesc> &plan)
+{
+    auto work = [](const BatchDesc &d) { return (double)d.m * d.n * d.n - (double)d.n * d.n * d.n / 3.0 + d.n; };
+    std::stable_sort(plan.begin(), plan.end(), [&](const BatchDesc &x, const BatchDesc &y) { return work(x) > work(y); });
+    double total = 0.0;
+    for (const BatchDesc &d : plan) total += work(d);
+    const double per = total / (2.0 * kCUs);
+    int used = 0;
+    std::vector<int> slots;
+    for (size_t q = 0; q < plan.size(); ++q) {
+        int t = (int)(work(plan[q]) / per);
+        if (t > kTeamMax) t = kTeamMax;
+        if (t < 2 || used + t > kTeamSlots)
+            t = 1;
+        else
+            used += t;
+        plan[q].team = t;
+        for (int k = 0; k < t; ++k) slots.push_back((int)q * kTeamMax + k);
+    }
+    return slots;
+}
+
 template <int P, int W, int R, int NT>
-int launch_batch(BatchArgs a, int maxgrid, hipStream_t s)
+int launch_batch(BatchArgs a, int count, int maxgrid, hipStream_t s)
 {
     int per_cu = 0, cus = 0, dev = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<P, W, R, NT>, NT, 0) != hipSuccess || per_cu < 1)
@@ -1626,10 +1694,13 @@ int launch_batch(BatchArgs a, int maxgrid, hipStream_t s)
     if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
                                                 hipSuccess || cus < 1)
         cus = kCUs;
+    // every workgroup of the grid is resident at once, so the members of every team meet
     int grid = per_cu * cus;
     if (grid > maxgrid) grid = maxgrid;
-    if (grid > a.count) grid = a.count;
-    MDLS_LAUNCH("k_zero", P, 0, k_zero_u32, dim3(1), dim3(64), s, a.counter, 1);
+    if (grid > count * kTeamMax) grid = count * kTeamMax;
+    const int nz = count * kTeamCtrs;
+    MDLS_LAUNCH("k_zero", P, 0, k_zero_u32, dim3(1), dim3(64), s, a.counter, 64);
+    MDLS_LAUNCH("k_zero", P, 0, k_zero_u32, dim3((nz + 255) / 256), dim3(256), s, a.tctr, nz);
     MDLS_LAUNCH("k_batch", P, 0, (k_batch<P, W, R, NT>), dim3(grid), dim3(NT), s, a);
     return hipGetLastError() == hipSuccess ? 0 : MDLS_EHIP;
 }
@@ -1639,27 +1710,32 @@ int batch_solve_t(int count, double *A, double *b, double *x, int variant, void 
                   hipStream_t s)
 {
     const BatchLayout L = batch_layout(P, count);
+    char *w = (char *)ws;
     BatchArgs a;
-    a.desc = (const BatchDesc *)((char *)ws + L.plan);
-    a.count = count;
+    a.desc = (const BatchDesc *)(w + L.plan);
+    a.slots = (const int *)(w + L.slots);
+    a.nslots = (const int *)(w + L.nslots);
     a.A = A;
     a.b = b;
     a.x = x;
-    a.scratch = (double *)((char *)ws + L.scratch);
-    a.counter = (unsigned *)((char *)ws + L.ctr);
+    a.scratch = (double *)(w + L.scratch);
+    a.counter = (unsigned *)(w + L.ctr);
+    a.err = (int *)(w + L.ctr) + 1;
+    a.tctr = (unsigned *)(w + L.tctr);
+    a.xch = (double *)(w + L.xch);
     a.info = d_info;
     a.times = d_times;
     if constexpr (P == 2) {
         switch (variant) {
-        case 0: return launch_batch<2, 8, 16, 256>(a, L.maxgrid, s);
-        case 1: return launch_batch<2, 8, 8, 512>(a, L.maxgrid, s);
-        case 2: return launch_batch<2, 4, 8, 256>(a, L.maxgrid, s);
+        case 0: return launch_batch<2, 8, 16, 256>(a, count, L.maxgrid, s);
+        case 1: return launch_batch<2, 8, 8, 512>(a, count, L.maxgrid, s);
+        case 2: return launch_batch<2, 4, 8, 256>(a, count, L.maxgrid, s);
         }
     } else if constexpr (P == 4) {
         switch (variant) {
-        case 0: return launch_batch<4, 4, 8, 256>(a, L.maxgrid, s);
-        case 1: return launch_batch<4, 4, 4, 512>(a, L.maxgrid, s);
-        case 2: return launch_batch<4, 8, 16, 256>(a, L.maxgrid, s);
+        case 0: return launch_batch<4, 4, 8, 256>(a, count, L.maxgrid, s);
+        case 1: return launch_batch<4, 4, 4, 512>(a, count, L.maxgrid, s);
+        case 2: return launch_batch<4, 8, 16, 256>(a, count, L.maxgrid, s);
         }
     }
     return MDLS_EUNSUPPORTED;
