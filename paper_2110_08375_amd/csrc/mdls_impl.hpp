@@ -84,6 +84,38 @@ __device__ inline void grid_sync(unsigned *ctr, unsigned target, int *err)
     __threadfence();
 }
 
+// Sum over a workgroup of per-thread partials of WW pairs: thread t holds a partial of pair
+// t % WW.  Partials of one pair inside a wave are combined with a butterfly, those of
+// different waves through LDS; out[q] (LDS, WW x P doubles) receives the renormalised total,
+// negated if NEG.  Called by every thread; ends with a workgroup barrier.
+template <int P, int WW, int NT, bool NEG>
+__device__ __forceinline__ void pair_sum(Acc<P> t, double *s_comb, double *out)
+{
+    constexpr int WV = (WW < 64) ? 64 : WW;  // threads that hold each pair once
+    constexpr int NP = NT / WV;              // partials per pair left after the butterfly
+    static_assert(NT % WV == 0, "pair_sum layout");
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int m = WW; m < 64; m <<= 1) acc_add_acc(t, shfl_xor_acc(t, m));
+    if (tid % WV < WW) {
+#pragma unroll
+        for (int k = 0; k < P; ++k) s_comb[((tid / WV) * WW + tid % WV) * P + k] = t.s[k];
+    }
+    __syncthreads();
+    for (int q = tid; q < WW; q += NT) {
+        Acc<P> s = acc_zero<P>();
+        for (int k = 0; k < NP; ++k) {
+            Acc<P> o;
+#pragma unroll
+            for (int e = 0; e < P; ++e) o.s[e] = s_comb[(k * WW + q) * P + e];
+            acc_add_acc(s, o);
+        }
+        const V<P> v = acc_get(s);
+        lds_st(&out[q * P], NEG ? neg(v) : v);
+    }
+    __syncthreads();
+}
+
 // Sum of NA lazy accumulators per lane over the row-slot bits of a wave (lane masks 32, 16,
 // ..., MMIN): while a lane holds two or more accumulators each level halves the set (the
 // partner keeps the other half), then plain butterfly levels follow.  Lane l keeps
@@ -183,6 +215,7 @@ __device__ __forceinline__ void panel_run(const PanelArgs &g, int bid)
     constexpr int SLOT = (W * W + 2 * W) * P;  // doubles per workgroup exchange slot
     static_assert(64 % W == 0 && S >= 2 * W && NW >= 4, "panel layout");
     __shared__ double s_part[NW * W * W * P];
+    __shared__ double s_comb[NT * P];     // pair_sum partials
     __shared__ double s_head[W * P];
     __shared__ double s_tot[W * P];       // column j's reduction: sigma (l = j), d_l, Gram sums
     __shared__ double s_hd[W * P];        // row j: a_jl
@@ -289,66 +322,51 @@ __device__ __forceinline__ void panel_run(const PanelArgs &g, int bid)
                 for (int k = 0; k < P; ++k) s_part[((wid * W + i0 + f) * W + c) * P + k] = sacc[f].s[k];
         }
         __syncthreads();
-        // pairs q = (i, cc) = (q / W, q % W); LP lanes per pair when W^2 < 64
+        // pairs q = (i, cc) = (q / W, q % W); thread t takes pair t % W^2 and every K-th part
+        // of its sums (K = NT / W^2 threads per pair), pair_sum combines them
         constexpr int WW = W * W;
-        constexpr int LP = (WW < 64) ? 64 / WW : 1;
-        if (wid == 0) {
-            for (int q0 = 0; q0 < WW; q0 += 64) {
-                const int q = q0 + lane % (WW < 64 ? WW : 64), sub = (WW < 64) ? lane / WW : 0;
-                Acc<P> t = acc_zero<P>();
-                for (int w = sub; w < NW; w += LP) {
-                    Acc<P> o;
+        constexpr int K = NT / WW;
+        const int pq = tid % WW, psub = tid / WW;
+        {
+            Acc<P> t = acc_zero<P>();
+            for (int w = psub; w < NW; w += K) {
+                Acc<P> o;
 #pragma unroll
-                    for (int k = 0; k < P; ++k) o.s[k] = s_part[(w * WW + q) * P + k];
-                    acc_add_acc(t, o);
-                }
-#pragma unroll
-                for (int m = WW; m < 64; m <<= 1) acc_add_acc(t, shfl_xor_acc(t, m));
-                if (g.G > 1) {
-                    if (sub == 0) {
-                        double *mine = g.gpart + (size_t)((nbar & 1) * g.G + bid) * SLOT;
-#pragma unroll
-                        for (int k = 0; k < P; ++k) st_coherent(mine + q * P + k, t.s[k]);
-                    }
-                } else if (sub == 0) {
-                    lds_st(&s_gram[q * P], acc_get(t));
-                }
+                for (int k = 0; k < P; ++k) o.s[k] = s_part[(w * WW + pq) * P + k];
+                acc_add_acc(t, o);
             }
-            if (g.G > 1) {
+            pair_sum<P, WW, NT, false>(t, s_comb, s_gram);  // this workgroup's S
+        }
+        if (g.G > 1) {
+            if (wid == 0) {
+                double *mine = g.gpart + (size_t)((nbar & 1) * g.G + bid) * SLOT;
+                for (int q = lane; q < WW; q += 64) {
+#pragma unroll
+                    for (int k = 0; k < P; ++k) st_coherent(mine + q * P + k, s_gram[q * P + k]);
+                }
                 grid_sync(g.gbar, (nbar + 1) * (unsigned)g.G, g.err);
-                const double *base = g.gpart + (size_t)((nbar & 1) * g.G) * SLOT;
-                for (int q0 = 0; q0 < WW; q0 += 64) {
-                    const int q = q0 + lane % (WW < 64 ? WW : 64), sub = (WW < 64) ? lane / WW : 0;
-                    Acc<P> t = acc_zero<P>();
-                    for (int b = sub; b < g.G; b += LP) {
-                        Acc<P> o;
-#pragma unroll
-                        for (int k = 0; k < P; ++k) o.s[k] = ld_coherent(base + (size_t)b * SLOT + q * P + k);
-                        acc_add_acc(t, o);
-                    }
-#pragma unroll
-                    for (int m = WW; m < 64; m <<= 1) acc_add_acc(t, shfl_xor_acc(t, m));
-                    if (sub == 0) lds_st(&s_gram[q * P], acc_get(t));
-                }
             }
+            __syncthreads();
+            const double *base = g.gpart + (size_t)((nbar & 1) * g.G) * SLOT;
+            Acc<P> t = acc_zero<P>();
+            for (int b = psub; b < g.G; b += K) {
+                Acc<P> o;
+#pragma unroll
+                for (int k = 0; k < P; ++k) o.s[k] = ld_coherent(base + (size_t)b * SLOT + pq * P + k);
+                acc_add_acc(t, o);
+            }
+            pair_sum<P, WW, NT, false>(t, s_comb, s_gram);
         }
         ++nbar;
-        __syncthreads();
-        // -U(i, cc) = -sum_{l<=i} T'(l, i) S(l, cc) into s_hrow (scratch); the LP lanes of a
+        // -U(i, cc) = -sum_{l<=i} T'(l, i) S(l, cc) into s_hrow (scratch); the K threads of a
         // pair split the sum over l
-        if (wid == 0) {
-            for (int q0 = 0; q0 < WW; q0 += 64) {
-                const int q = q0 + lane % (WW < 64 ? WW : 64), sub = (WW < 64) ? lane / WW : 0;
-                const int i = q / W, cc = q % W;
-                Acc<P> u = acc_zero<P>();
-                for (int l = sub; l <= i; l += LP)
-                    acc_fma(u, ldm<P>(g.Tp, g.tps, (long)i * W + l), lds_ld<P>(&s_gram[(l * W + cc) * P]));
-#pragma unroll
-                for (int m = WW; m < 64; m <<= 1) acc_add_acc(u, shfl_xor_acc(u, m));
-                if (sub == 0) lds_st(&s_hrow[q * P], neg(acc_get(u)));
-            }
+        {
+            const int i = pq / W, cc = pq % W;
+            Acc<P> u = acc_zero<P>();
+            for (int l = psub; l <= i; l += K)
+                acc_fma(u, ldm<P>(g.Tp, g.tps, (long)i * W + l), lds_ld<P>(&s_gram[(l * W + cc) * P]));
+            pair_sum<P, WW, NT, true>(u, s_comb, s_hrow);
         }
-        __syncthreads();
 #pragma unroll
         for (int k = 0; k < R; ++k) {
             const long r = rbase + k * rstride;
