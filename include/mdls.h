@@ -133,7 +133,12 @@ const char *mdls_status_string(int status);
  *                              workspace keeps the plan).  variant selects the kernel shape
  *                              (0 <= variant < mdls_batch_variants(p)).  d_info (count device
  *                              ints) receives each problem's status as *d_info of
- *                              mdls_solve; d_times (2 count device long longs, or null) the
+ *                              mdls_solve, or -1 if the workgroups sharing the problem timed
+ *                              out at one of their barriers (x then unspecified; the largest
+ *                              problems of a batch are shared by up to 16 workgroups, which
+ *                              needs every workgroup of the launch resident at once, as it is
+ *                              when nothing else occupies the GPU); d_times (2 count device
+ *                              long longs, or null) the
  *                              start and end of each problem in wall-clock ticks
  *                              (mdls_wall_clock_khz).
  *   mdls_batch_variants(p)     number of kernel variants (0 if p is not supported).
