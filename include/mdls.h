@@ -156,6 +156,24 @@ typedef struct {
     long long a_off, b_off, x_off;
 } mdls_batch_desc;
 
+/*
+ * Refined least squares (the precision form): the accuracy of p_out = 4 (qd) or 8 (od) limbs
+ * from a double-double factorisation.  A (m x n, double double, ld lda, read only) is copied
+ * into F (same shape and ld, overwritten by its dd factors); Householder QR of F in dd with
+ * the tile T factors (Section 3); then iters refinement steps, each: r := b - A x formed in
+ * p_out limbs (x = 0 in the first), d := R^-1 (Q^T r)(0:n) in dd (r rounded to dd; Q^T by the
+ * tile reflectors, R^-1 by the tiled back substitution of Section 2), x += d in p_out limbs.
+ * b: P = p_out planes of m; x: p_out planes of n (output).  Each step gains about
+ * -log10(kappa(A) 2^-105) digits while kappa(A) 2^-105 << 1 and b is consistent (b = A x*);
+ * d_norms (2 iters device doubles) receives max |d| and max |x| (leading limbs) of each step,
+ * so the caller can see the convergence.  *d_info as for mdls_solve.  n % tile == 0.
+ *   mdls_refined_workspace_bytes(p_out, m, n, tile)   workspace (0 if arguments invalid).
+ */
+size_t mdls_refined_workspace_bytes(int p_out, int m, int n, int tile);
+int mdls_solve_refined(int p_out, int m, int n, int tile, const double *A, int lda, const double *b,
+                       double *x, int iters, double *F, void *ws, size_t ws_bytes, int *d_info,
+                       double *d_norms, hipStream_t stream);
+
 size_t mdls_batch_workspace_bytes(int p, int count);
 int mdls_batch_plan(int p, int count, const mdls_batch_desc *h_desc, void *ws, size_t ws_bytes,
                     hipStream_t stream);

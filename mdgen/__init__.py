@@ -44,6 +44,8 @@ STREAM_A = 1
 STREAM_X = 2
 STREAM_B = 3
 STREAM_DIAG = 4
+STREAM_U = 7
+STREAM_V = 8
 
 
 def _mix_int(z: int) -> int:
@@ -246,6 +248,23 @@ def upper_triangular_exact(P: int, n: int, seed: int, device=None):
     bv = torch.zeros((P, n), dtype=torch.float64, device=device)
     bv[0] = R[0].sum(dim=0)
     return R, bv
+
+
+def conditioned(P: int, m: int, n: int, seed: int, kappa: float = 1e8, reflectors: int = 8):
+    """A = U diag(s) V^T (m x n) with s log-spaced from 1 down to 1/kappa, U and V products of
+    `reflectors` Householder reflectors I - 2 u u^T / u^T u with uniform u (the precision-form
+    workload); formed in float64 (numpy) as limb 0, lower limbs drawn as in md_uniform.
+    Shape (P, n, m)."""
+    s = np.logspace(0.0, -math.log10(kappa), n)
+    M = np.zeros((m, n))
+    M[np.arange(n), np.arange(n)] = s
+    for k in range(reflectors):
+        u = uniform(seed, STREAM_U, m, k * m)
+        M -= np.outer(u, (2.0 / (u @ u)) * (u @ M))
+    for k in range(reflectors):
+        v = uniform(seed, STREAM_V, n, k * n)
+        M -= np.outer((2.0 / (v @ v)) * (M @ v), v)
+    return md_from_leading(np.ascontiguousarray(M.T), P, seed, STREAM_A, 0)
 
 
 def ls_problem(P: int, m: int, n: int, seed: int, ones_solution: bool = False, device=None):

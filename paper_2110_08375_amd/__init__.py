@@ -21,7 +21,9 @@ from .mdls import (  # noqa: F401
     lib,
     max_rows,
     qr,
+    refined_workspace,
     solve,
+    solve_refined,
     solve_batched,
     status_string,
     timing_enable,

@@ -15,6 +15,8 @@ MDLS_FOR_PRECISION(extern, 4)
 MDLS_FOR_PRECISION(extern, 8)
 MDLS_BATCH_FOR_PRECISION(extern, 2)
 MDLS_BATCH_FOR_PRECISION(extern, 4)
+MDLS_REFINE_FOR_PRECISION(extern, 4)
+MDLS_REFINE_FOR_PRECISION(extern, 8)
 }  // namespace mdls_impl
 
 using namespace mdls_impl;
@@ -352,6 +354,35 @@ int mdls_wall_clock_khz(int *khz)
     if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess)
         return MDLS_EHIP;
     return 0;
+}
+
+size_t mdls_refined_workspace_bytes(int p_out, int m, int n, int tile)
+{
+    if ((p_out != 4 && p_out != 8) || n < 1 || m < n || !valid_tile(tile)) return 0;
+    return align256(layout(2, m, n, tile).total) + refine_extra_bytes(p_out, m, n, tile);
+}
+
+int mdls_solve_refined(int p_out, int m, int n, int tile, const double *A, int lda, const double *b, double *x,
+                       int iters, double *F, void *ws, size_t ws_bytes, int *d_info, double *d_norms,
+                       hipStream_t stream)
+{
+    if (p_out != 4 && p_out != 8) return -1;
+    if (m < 1) return -2;
+    if (n < 1 || n > m) return -3;
+    if (!valid_tile(tile) || n % tile != 0) return -4;
+    if (!A) return -5;
+    if (lda < m) return -6;
+    if (!b) return -7;
+    if (!x) return -8;
+    if (iters < 1 || iters > 64) return -9;
+    if (!F) return -10;
+    if (!ws) return -11;
+    if (ws_bytes < mdls_refined_workspace_bytes(p_out, m, n, tile)) return -12;
+    if (!d_info) return -13;
+    if (!d_norms) return -14;
+    if (m > mdls_max_rows(2)) return MDLS_EUNSUPPORTED;
+    if (p_out == 4) return refine_t<4>(m, n, tile, A, lda, b, x, iters, F, ws, d_info, d_norms, stream);
+    return refine_t<8>(m, n, tile, A, lda, b, x, iters, F, ws, d_info, d_norms, stream);
 }
 
 int mdls_timing_enable(int on)

@@ -992,6 +992,75 @@ __global__ __launch_bounds__(NT) void k_batch(BatchArgs g)
     }
 }
 
+// ============================================================================ iterative refinement
+// Mixed-precision kernels of the refined solve: the residual r = b - A x of a PA-limb matrix
+// and a PX-limb vector, formed in PX limbs, and x += d with running maxima of |d| and |x|.
+constexpr int kResidCols = 128;  // columns per residual chunk
+
+// part[ch][k][i] = level sums of sum_{j in chunk ch} A_ij x_j (not renormalised), one row per
+// thread, chunk ch = blockIdx.y of kResidCols columns
+template <int PA, int PX>
+__global__ __launch_bounds__(kThreads) void k_resid_part(const double *A, long lda, long psa, int m, int n,
+                                                         const double *x, long xps, double *part)
+{
+    __shared__ double sx[kResidCols * PX];
+    const int c0 = blockIdx.y * kResidCols;
+    const int c1 = (n - c0 < kResidCols) ? n : c0 + kResidCols;
+    for (int j = threadIdx.x; j < c1 - c0; j += kThreads) lds_st(&sx[j * PX], ldm<PX>(x, xps, c0 + j));
+    __syncthreads();
+    const long i = (long)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= m) return;
+    Acc<PX> acc = acc_zero<PX>();
+    for (int j = c0; j < c1; ++j) {
+        const V<PA> a = ldm<PA>(A, psa, (long)j * lda + i);
+        const V<PX> xv = lds_ld<PX>(&sx[(j - c0) * PX]);
+        casc_fma<PX, PA, PX, 0, 0, true>(acc.s, a.x, xv.x, nullptr);
+        if (((j - c0 + 1) % kLazy<PX>) == 0) acc = acc_from(acc_get(acc));
+    }
+#pragma unroll
+    for (int k = 0; k < PX; ++k) part[((long)blockIdx.y * PX + k) * m + i] = acc.s[k];
+}
+
+// r_i = b_i - sum_ch part[ch][.][i] (chunks in order)
+template <int PX>
+__global__ __launch_bounds__(kThreads) void k_resid_fin(const double *b, long bps, const double *part, int m, int nch,
+                                                        double *r, long rps)
+{
+    const long i = (long)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= m) return;
+    Acc<PX> t = acc_from(ldm<PX>(b, bps, i));
+    for (int ch = 0; ch < nch; ++ch) {
+        V<PX> o;
+#pragma unroll
+        for (int k = 0; k < PX; ++k) o.x[k] = -part[((long)ch * PX + k) * m + i];
+        acc_add(t, o);
+    }
+    stm(r, rps, i, acc_get(t));
+}
+
+// x_i += d_i (d of PD <= PX limbs); norms[0] = max |d_i|, norms[1] = max |x_i| (leading limbs;
+// non-negative doubles ordered as their bit patterns)
+template <int PX, int PD>
+__global__ __launch_bounds__(kThreads) void k_refine_add(double *x, long xps, const double *d, long dps, int n,
+                                                         unsigned long long *norms)
+{
+    const long i = (long)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n) return;
+    const V<PD> dv = ldm<PD>(d, dps, i);
+    const V<PX> xn = add(ldm<PX>(x, xps, i), resize<PX>(dv));
+    stm(x, xps, i, xn);
+    atomicMax(&norms[0], (unsigned long long)__double_as_longlong(fabs(dv.x[0])));
+    atomicMax(&norms[1], (unsigned long long)__double_as_longlong(fabs(xn.x[0])));
+}
+
+namespace {
+__global__ void k_zero_f64(double *p, long n)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+}  // namespace
+
 // ============================================================================ small kernels
 namespace {
 __global__ void k_zero_u32(unsigned *p, int n)
@@ -1761,6 +1830,65 @@ int batch_solve_t(int count, double *A, double *b, double *x, int variant, void 
 
 #define MDLS_BATCH_FOR_PRECISION(X, P) \
     X template int batch_solve_t<P>(int, double *, double *, double *, int, void *, int *, long long *, hipStream_t);
+
+// ---------------------------------------------------------------- refined solve (host)
+// Least squares to PX limbs from a double-double factorisation: F := A, QR of F in dd (with
+// the tile T factors), x := 0, r := b; then `iters` times: d := R^-1 (Q^T r)(0:n) in dd (r
+// rounded to dd), x += d, r := b - A x in PX limbs.  Converges when kappa(A) 2^-105 << 1;
+// norms[2 it], norms[2 it + 1] receive max |d| and max |x| of iteration it.
+inline size_t refine_extra_bytes(int px, int m, int n, int tile)
+{
+    const size_t nch = (size_t)(n + kResidCols - 1) / kResidCols;
+    return sizeof(double) * (2 * (size_t)n * tile + (size_t)px * m + 2 * (size_t)m + 2 * (size_t)n + nch * px * m) +
+           5 * 256;
+}
+
+template <int PX>
+int refine_t(int m, int n, int tile, const double *A, int lda, const double *b, double *x, int iters, double *F,
+             void *ws, int *d_info, double *norms, hipStream_t s)
+{
+    const Layout L = layout(2, m, n, tile);
+    char *e = (char *)ws + align256(L.total);
+    auto take = [&](size_t doubles) {
+        double *p = (double *)e;
+        e += align256(sizeof(double) * doubles);
+        return p;
+    };
+    const int nch = (n + kResidCols - 1) / kResidCols;
+    double *T = take(2 * (size_t)n * tile);
+    double *r = take((size_t)PX * m);
+    double *rdd = take(2 * (size_t)m);
+    double *dd = take(2 * (size_t)n);
+    double *part = take((size_t)nch * PX * m);
+    const long psa = (long)lda * n;
+    MDLS_LAUNCH("k_copy", PX, 0, k_copy, dim3((unsigned)((psa + 255) / 256)), dim3(256), s, A, psa, F, psa, (int)psa, 2);
+    MDLS_LAUNCH("k_copy", PX, 0, k_copy, dim3((m + 255) / 256), dim3(256), s, b, (long)m, r, (long)m, m, PX);
+    MDLS_LAUNCH("k_zero", PX, 0, k_zero_f64, dim3((PX * n + 255) / 256), dim3(256), s, x, (long)PX * n);
+    MDLS_LAUNCH("k_zero", PX, 0, k_zero_f64, dim3((2 * iters + 255) / 256), dim3(256), s, norms, (long)2 * iters);
+    int rc = qr_t<2>(m, n, tile, F, lda, T, tile, ws, s);
+    for (int it = 0; it < iters && rc == 0; ++it) {
+        if (it > 0) {
+            MDLS_LAUNCH("k_resid_part", PX, (double)m * n, (k_resid_part<2, PX>), dim3((m + kThreads - 1) / kThreads, nch),
+                        dim3(kThreads), s, A, (long)lda, psa, m, n, x, (long)n, part);
+            MDLS_LAUNCH("k_resid_fin", PX, 0, (k_resid_fin<PX>), dim3((m + kThreads - 1) / kThreads), dim3(kThreads), s, b,
+                        (long)m, part, m, nch, r, (long)m);
+        }
+        MDLS_LAUNCH("k_copy", PX, 0, k_copy, dim3((m + 255) / 256), dim3(256), s, r, (long)m, rdd, (long)m, m, 2);
+        rc = apply_qt_t<2>(m, n, tile, F, lda, T, tile, rdd, m, 1, ws, s);
+        if (rc != 0) break;
+        MDLS_LAUNCH("k_copy", PX, 0, k_copy, dim3((n + 255) / 256), dim3(256), s, rdd, (long)m, dd, (long)n, n, 2);
+        rc = backsub_t<2>(n, tile, F, lda, dd, ws, d_info, s);
+        if (rc != 0) break;
+        MDLS_LAUNCH("k_refine_add", PX, 0, (k_refine_add<PX, 2>), dim3((n + kThreads - 1) / kThreads), dim3(kThreads), s,
+                    x, (long)n, dd, (long)n, n, (unsigned long long *)(norms + 2 * it));
+    }
+    if (rc != 0) return rc;
+    return hipGetLastError() == hipSuccess ? 0 : MDLS_EHIP;
+}
+
+#define MDLS_REFINE_FOR_PRECISION(X, P) \
+    X template int refine_t<P>(int, int, int, const double *, int, const double *, double *, int, double *, void *, \
+                               int *, double *, hipStream_t);
 
 #define MDLS_FOR_PRECISION(X, P)                                                                        \
     X template int solve_t<P>(int, int, int, double *, int, double *, double *, void *, int *, hipStream_t);     \

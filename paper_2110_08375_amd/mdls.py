@@ -21,7 +21,8 @@ MDLS_EHIP, MDLS_EUNSUPPORTED = -100, -101
 EXPORTS = ("mdls_max_rows", "mdls_workspace_bytes", "mdls_qr", "mdls_apply_qt", "mdls_form_w",
            "mdls_backsub", "mdls_solve", "mdls_status_string", "mdls_timing_enable", "mdls_timing_reset",
            "mdls_timing_query", "mdls_timing_kernels", "mdls_batch_workspace_bytes", "mdls_batch_plan",
-           "mdls_solve_batched", "mdls_batch_variants", "mdls_batch_autotune", "mdls_wall_clock_khz")
+           "mdls_solve_batched", "mdls_batch_variants", "mdls_batch_autotune", "mdls_wall_clock_khz",
+           "mdls_refined_workspace_bytes", "mdls_solve_refined")
 
 
 class BatchDesc(ctypes.Structure):
@@ -69,9 +70,13 @@ def lib():
         L.mdls_batch_autotune.argtypes = [i, i, vp, vp, sz, sz, vp, vp, vp, vp, sz, vp, ctypes.POINTER(ctypes.c_float),
                                           vp]
         L.mdls_wall_clock_khz.argtypes = [ctypes.POINTER(ctypes.c_int)]
+        L.mdls_refined_workspace_bytes.argtypes = [i, i, i, i]
+        L.mdls_refined_workspace_bytes.restype = sz
+        L.mdls_solve_refined.argtypes = [i, i, i, i, vp, i, vp, vp, i, vp, vp, sz, vp, vp, vp]
         for f in ("mdls_qr", "mdls_apply_qt", "mdls_form_w", "mdls_backsub", "mdls_solve", "mdls_timing_enable",
                   "mdls_timing_reset", "mdls_timing_query", "mdls_timing_kernels", "mdls_batch_plan",
-                  "mdls_solve_batched", "mdls_batch_variants", "mdls_batch_autotune", "mdls_wall_clock_khz"):
+                  "mdls_solve_batched", "mdls_batch_variants", "mdls_batch_autotune", "mdls_wall_clock_khz",
+           "mdls_refined_workspace_bytes", "mdls_solve_refined"):
             getattr(L, f).restype = i
         _lib = L
     return _lib
@@ -280,3 +285,38 @@ def wall_clock_khz() -> int:
     k = ctypes.c_int(0)
     _check(lib().mdls_wall_clock_khz(ctypes.byref(k)), "mdls_wall_clock_khz")
     return k.value
+
+
+# ----------------------------------------------------------------------------- refined solve
+def refined_workspace(p_out: int, m: int, n: int, tile: int, device="cuda"):
+    import torch
+
+    nb = lib().mdls_refined_workspace_bytes(p_out, m, n, tile)
+    if nb == 0:
+        raise ValueError("invalid sizes for a refined-solve workspace")
+    return torch.empty(nb, dtype=torch.uint8, device=device)
+
+
+def solve_refined(p_out: int, A, b, tile: int, iters: int, x=None, F=None, ws=None, info=None, norms=None):
+    """x (p_out, n) from a double-double factorisation of A (2, n, m) and iters refinement steps
+    with residuals in p_out limbs; b (p_out, m).  Returns (x, info, norms); norms (2 iters) holds
+    max |correction| and max |x| per step."""
+    import torch
+
+    m, n = _mat(A, 2, "A")
+    _vec(b, p_out, "b", m)
+    if x is None:
+        x = torch.empty((p_out, n), dtype=torch.float64, device=A.device)
+    _vec(x, p_out, "x", n)
+    if F is None:
+        F = torch.empty_like(A)
+    if ws is None:
+        ws = refined_workspace(p_out, m, n, tile, A.device)
+    if info is None:
+        info = torch.zeros(1, dtype=torch.int32, device=A.device)
+    if norms is None:
+        norms = torch.zeros(2 * iters, dtype=torch.float64, device=A.device)
+    rc = lib().mdls_solve_refined(p_out, m, n, tile, _ptr(A), m, _ptr(b), _ptr(x), iters, _ptr(F), _ptr(ws), ws.numel(),
+                                  _ptr(info), _ptr(norms), _stream())
+    _check(rc, "mdls_solve_refined")
+    return x, info, norms

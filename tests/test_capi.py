@@ -116,3 +116,18 @@ def test_batched_entry_point_errors(L):
     assert sb(2, 3, None, d, d, 0, d, ws, d, None, None) == -3
     assert sb(2, 3, d, d, d, 0, d, ws, None, None, None) == -9
     assert sb(4, 3, d, d, d, 0, d, L.mdls_batch_workspace_bytes(4, 3) - 1, d, None, None) == -8
+
+
+def test_refined_entry_point_errors(L):
+    d = ctypes.c_void_p(16)
+    assert L.mdls_refined_workspace_bytes(8, 256, 256, 64) > L.mdls_workspace_bytes(2, 256, 256, 64)
+    assert L.mdls_refined_workspace_bytes(2, 256, 256, 64) == 0
+    ws = L.mdls_refined_workspace_bytes(8, 64, 32, 16)
+    f = L.mdls_solve_refined
+    assert f(2, 64, 32, 16, d, 64, d, d, 4, d, d, ws, d, d, None) == -1
+    assert f(8, 64, 30, 16, d, 64, d, d, 4, d, d, ws, d, d, None) == -4
+    assert f(8, 64, 32, 16, d, 63, d, d, 4, d, d, ws, d, d, None) == -6
+    assert f(4, 64, 32, 16, d, 64, d, d, 0, d, d, ws, d, d, None) == -9
+    assert f(8, 64, 32, 16, d, 64, d, d, 4, None, d, ws, d, d, None) == -10
+    assert f(8, 64, 32, 16, d, 64, d, d, 4, d, d, ws - 1, d, d, None) == -12
+    assert f(8, 64, 32, 16, d, 64, d, d, 4, d, d, ws, d, None, None) == -14

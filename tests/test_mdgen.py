@@ -73,3 +73,11 @@ def test_upper_triangular_exact_rhs_is_exact():
         assert np.all(np.tril(R[0].T, -1) == 0.0)
         Rt, bt = mdgen.upper_triangular_exact(4, n, 7, device="cpu")
         assert np.array_equal(Rt.numpy(), R) and np.array_equal(bt.numpy(), b)
+
+
+def test_conditioned_matrix_has_requested_kappa():
+    A = mdgen.conditioned(2, 120, 80, 3, kappa=1e6)
+    assert A.shape == (2, 80, 120)
+    s = np.linalg.svd(A[0].T, compute_uv=False)
+    assert abs(s[0] - 1.0) < 1e-9 and abs(s[-1] / 1e-6 - 1.0) < 1e-6
+    assert np.all(np.abs(A[1]) <= np.spacing(np.abs(A[0])))
