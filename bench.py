@@ -14,7 +14,8 @@ fraction of the FP64 peak; a roofline entry for the kernel that takes the most d
 (per-kernel HIP-event timing inside the library, on the solve's stream); and the CPU oracle
 timed on a bounded sample of the same workload; and the batched form (512 uneven dd and qd
 problems in one persistent launch: solves/s, p50/p99 per-problem latency) against the plain
-solver called once per problem.
+solver called once per problem; and the precision form (n = 2048, kappa = 1e8: double-double
+factorisation refined with qd/od residuals) against the plain qd/od solver.
 """
 from __future__ import annotations
 
@@ -164,6 +165,48 @@ def batched_run(M, P, count, seed, dev, reps, per_problem):
     return out
 
 
+def precision_run(M, dev, n=2048, tile=128):
+    """The precision form: m = n = 2048, kappa = 1e8 (U diag(s) V^T), factor in dd and refine with
+    qd / od residuals, against the plain solver at the target precision (timing only; the
+    accuracy of both is checked in tests/test_gpu_refine.py)."""
+    import numpy as np
+    import torch
+
+    import mdgen
+
+    A = mdgen.conditioned(2, n, n, 77, kappa=1e8)
+    out = {"workload": "least squares m=n=%d, tile %d, kappa 1e8 (U diag(s) V^T, 8 reflectors each), factor in "
+                       "dd, refine with qd/od residuals, vs the plain solver at qd/od; random right-hand side "
+                       "(timing only)" % (n, tile)}
+    Ag = torch.from_numpy(A).to(dev)
+    for P, iters in ((4, 4), (8, 6)):
+        b = torch.from_numpy(mdgen.md_vector(P, n, 78, mdgen.STREAM_B)).to(dev)
+        ws = M.refined_workspace(P, n, n, tile, dev)
+        F = torch.empty_like(Ag)
+        ms = []
+        for _ in range(2):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            M.solve_refined(P, Ag, b, tile, iters, F=F, ws=ws)
+            e1.record()
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        Ap = torch.zeros((P, n, n), dtype=torch.float64, device=dev)
+        Ap[:2] = Ag
+        bp = b.clone()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        M.solve(P, Ap, bp, tile)
+        e1.record()
+        torch.cuda.synchronize()
+        mp = e0.elapsed_time(e1)
+        out[PNAME[P]] = {"refined_ms": round(ms[-1], 3), "iters": iters, "plain_ms": round(mp, 3),
+                         "speedup": round(mp / ms[-1], 2)}
+        log("precision form %s: refined %.2f ms, plain %.2f ms" % (PNAME[P], ms[-1], mp))
+        del Ap, bp, F, ws
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -177,6 +220,7 @@ def main():
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-solves measurement")
     ap.add_argument("--batch", type=int, default=512)
+    ap.add_argument("--no-precision", action="store_true", help="skip the refined (precision-form) measurement")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -299,6 +343,8 @@ def main():
         for P in (2, 4):
             batched[PNAME[P]] = batched_run(M, P, args.batch, 4000 + P, dev, 3, True)
 
+    precision = None if args.no_precision else precision_run(M, dev)
+
     cpu = None
     if not args.no_cpu_baseline:
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -328,6 +374,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "batched": batched,
+        "precision_form": precision,
     }
     print(json.dumps(out), flush=True)
 
