@@ -265,3 +265,38 @@ def test_backsub_full_size_exact_rhs(M):
     for i in range(0, n, 997):  # exact check of a sample
         v = sum(Fraction(float(xh[k, i])) for k in range(P))
         assert abs(v - 1) <= Fraction(TOL[P] * 10)
+
+
+def test_solve_graph_replay(M):
+    """A least-squares solve (look-ahead side stream included) captured in a graph and replayed
+    three times, with eager restores of A and b between replays: each replay equals the eager
+    solve bit for bit."""
+    P, m, n, tile = 4, 300, 128, 32
+    A, _ = mdgen.ls_problem(P, m, n, 12)
+    b = mdgen.md_vector(P, m, 12, 3)
+    A0, b0 = to_gpu(A), to_gpu(b)
+    Aw, bw = A0.clone(), b0.clone()
+    x = torch.zeros((P, n), dtype=torch.float64, device=dev())
+    ws = M.workspace(P, m, n, tile, dev())
+    info = torch.zeros(1, dtype=torch.int32, device=dev())
+    M.solve(P, Aw, bw, tile, x=x, ws=ws, info=info)
+    torch.cuda.synchronize()
+    ref = x.cpu().numpy().copy()
+    Aw.copy_(A0)
+    bw.copy_(b0)
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=s):
+        M.solve(P, Aw, bw, tile, x=x, ws=ws, info=info)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        Aw.copy_(A0)
+        bw.copy_(b0)
+        x.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(x.cpu().numpy(), ref), rep
+        assert int(info.item()) == 0
