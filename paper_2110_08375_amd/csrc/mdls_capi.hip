@@ -79,14 +79,23 @@ bool lookahead_on()
     return !(e && e[0] == '0');
 }
 
-int apply_grid_cap()
+// Workgroups of a concurrent trailing update of h rows (grid-stride beyond): two per CU for dd
+// and qd, whose panels have slack; for od, whose panel and update are balanced, two per CU only
+// while the update is much longer than the panel (measured on the n = 1024 solves).
+// MDLS_APPLY_GRID_CAP overrides.
+int apply_grid_cap(int P, int h)
 {
     const char *e = getenv("MDLS_APPLY_GRID_CAP");
     if (e) {
         const int v = atoi(e);
         if (v > 0) return v;
     }
-    return 224;
+    if (P < 8) return 448;
+    // od: two per CU too while the update is much longer than the panel (h >= 768 rows), then
+    // one per CU on 224 CUs
+    const char *w = getenv("MDLS_APPLY_WIDE_ROWS");
+    const int wide = w ? atoi(w) : 768;
+    return h >= wide ? 448 : 224;
 }
 
 void timing_begin(hipStream_t s, void **ev)

@@ -1311,7 +1311,7 @@ struct SideStream {
 };
 SideStream *side_stream();
 bool lookahead_on();
-int apply_grid_cap();
+int apply_grid_cap(int P, int h);
 
 #define MDLS_LAUNCH(NAME, PREC, WORK, KERNEL, GRID, BLOCK, STREAM, ...)                       \
     do {                                                                                     \
@@ -1511,7 +1511,6 @@ void qr_panels(const Ctx<P> &cx, int m, int n, double *A, long lda, long psa, do
     MDLS_LAUNCH("k_zero", P, 0, k_zero_u32, dim3(1), dim3(256), cx.s, (unsigned *)cx.err(), 4);
     const long tps = (long)W * W * nleaves;
     SideStream *ss = (nleaves > 1 && lookahead_on()) ? side_stream() : nullptr;
-    const int cap = ss ? apply_grid_cap() : 0;
     for (int l = 0; l < nleaves; ++l) {
         const int c0 = l * W;
         const int wact = (n - c0 < W) ? (n - c0) : W;
@@ -1561,7 +1560,7 @@ void qr_panels(const Ctx<P> &cx, int m, int n, double *A, long lda, long psa, do
         if (ss) {
             hipEventRecord(ss->ev_panel, cx.s);
             hipStreamWaitEvent(ss->q, ss->ev_panel, 0);
-            launch_apply<P>(cx, aa, cap, ss->q);
+            launch_apply<P>(cx, aa, apply_grid_cap(P, h), ss->q);
             hipEventRecord(ss->ev_wide[l & 1], ss->q);
         } else {
             launch_apply<P>(cx, aa, 0, cx.s);
