@@ -840,12 +840,24 @@ struct BatchArgs {
 // C := C - Y T^T (Y^T C) for the ncols columns at C0 (plane stride ps, ld lda) and the column
 // b0 (plane stride bps, index ncols), h rows from the panel's diagonal; one column per wave,
 // columns first, first + step, ... for this wave.
-template <int P, int W, int NT>
+template <int P, int W, int NT, bool STAGED>
 __device__ __forceinline__ void batch_update(const double *Y, long lda, long ps, int h, int wact, const double *T,
-                                             double *C0, int ncols, double *b0, long bps, int first, int step)
+                                             double *C0, int ncols, double *b0, long bps, int first, int step,
+                                             const double *sY)
 {
     constexpr int LPI = 64 / W, NQ = (W * W + 63) / 64;
     const int lane = threadIdx.x & 63;
+    // Y(r, i): from the LDS copy (limb k of column i at sY[(i P + k) kBatchRows + r]) or global
+    auto yv = [&](int r, int i) __attribute__((always_inline)) {
+        if constexpr (STAGED) {
+            V<P> y;
+#pragma unroll
+            for (int k = 0; k < P; ++k) y.x[k] = sY[(i * P + k) * kBatchRows + r];
+            return y;
+        } else {
+            return y_entry<P>(Y, lda, ps, r, i, h, wact);
+        }
+    };
     for (int col = first; col <= ncols; col += step) {
         double *cp = (col < ncols) ? C0 + (long)col * lda : b0;
         const long cps = (col < ncols) ? ps : bps;
@@ -856,7 +868,7 @@ __device__ __forceinline__ void batch_update(const double *Y, long lda, long ps,
         for (int r = lane; r < h; r += 64) {
             const V<P> cv = ldm<P>(cp, cps, r);
 #pragma unroll
-            for (int i = 0; i < W; ++i) acc_fma_step(s[i], y_entry<P>(Y, lda, ps, r, i, h, wact), cv, nt);
+            for (int i = 0; i < W; ++i) acc_fma_step(s[i], yv(r, i), cv, nt);
             ++nt;
         }
         reduce_scatter<P, W>(s, lane);
@@ -880,7 +892,7 @@ __device__ __forceinline__ void batch_update(const double *Y, long lda, long ps,
         for (int r = lane; r < h; r += 64) {
             Acc<P> t = acc_from(ldm<P>(cp, cps, r));
 #pragma unroll
-            for (int i = 0; i < W; ++i) acc_fma(t, y_entry<P>(Y, lda, ps, r, i, h, wact), nU[i]);
+            for (int i = 0; i < W; ++i) acc_fma(t, yv(r, i), nU[i]);
             stm(cp, cps, r, acc_get(t));
         }
     }
@@ -922,6 +934,8 @@ __global__ __launch_bounds__(NT) void k_batch(BatchArgs g)
     constexpr int NW = NT / 64;
     constexpr long WWP = (long)W * W * P;
     constexpr long XCHP = WWP + 2L * kTeamMax * (W * W + 2 * W) * P;
+    constexpr bool STAGED = W * P <= 16;  // the panel's Y staged in LDS (at most 64 KiB)
+    __shared__ double sY[STAGED ? W * P * kBatchRows : 1];
     __shared__ double s_y[kBatchRows * P];
     __shared__ double s_r[kBatchRows * P];
     __shared__ int s_next, s_zero;
@@ -973,8 +987,17 @@ __global__ __launch_bounds__(NT) void k_batch(BatchArgs g)
             pa.G = team;
             panel_run<P, W, R, NT>(pa, mem);
             team_sync();
-            batch_update<P, W, NT>(pa.A, lda, ps, pa.h, pa.wact, pa.T, A + (long)(c0 + pa.wact) * lda + c0,
-                                   d.n - c0 - pa.wact, bp + c0, d.m, mem * NW + wid, team * NW);
+            if constexpr (STAGED) {
+                for (int e = threadIdx.x; e < W * pa.h; e += NT) {
+                    const int r = e % pa.h, i = e / pa.h;
+                    const V<P> y = y_entry<P>(pa.A, lda, ps, r, i, pa.h, pa.wact);
+#pragma unroll
+                    for (int k = 0; k < P; ++k) sY[(i * P + k) * kBatchRows + r] = y.x[k];
+                }
+                __syncthreads();
+            }
+            batch_update<P, W, NT, STAGED>(pa.A, lda, ps, pa.h, pa.wact, pa.T, A + (long)(c0 + pa.wact) * lda + c0,
+                                           d.n - c0 - pa.wact, bp + c0, d.m, mem * NW + wid, team * NW, sY);
             __syncthreads();
             team_sync();
         }

@@ -218,7 +218,7 @@ def test_run_to_run_bitwise(M):
 
 
 @pytest.mark.parametrize("P,m,n,tile", [(2, 1024, 1024, 128), (2, 2048, 1024, 128), (4, 1024, 1024, 128),
-                                        (8, 1024, 1024, 128)])
+                                        (4, 2048, 1024, 128), (8, 1024, 1024, 128), (8, 2048, 1024, 128)])
 def test_full_size_recovers_x_true(M, orc, P, m, n, tile):
     """The n = 1024 headline sizes: b = A x_true formed exactly by the oracle and rounded to P
     limbs, so the computed x must match x_true to the kappa-scaled tolerance."""
