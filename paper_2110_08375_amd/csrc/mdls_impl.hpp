@@ -1137,6 +1137,7 @@ __global__ __launch_bounds__(kThreads) void k_invert(InvArgs g)
     constexpr int RG = kThreads / NC;  // row groups
     __shared__ double sD[256 * P];
     __shared__ double sX[2][NC * P];
+    __shared__ double sU[2][256 * P];  // column i of the tile; column i-1 is loaded during step i
     const int t = blockIdx.y;
     const int c0 = blockIdx.x * NC;
     const int tid = threadIdx.x;
@@ -1161,9 +1162,14 @@ __global__ __launch_bounds__(kThreads) void k_invert(InvArgs g)
         r[q] = (k == j) ? from_double<P>(1.0) : zero<P>();
         if (j < g.tile && k < g.tile && k > j) stm(X, g.psx, (long)j * g.ldx + k, zero<P>());
     }
+    if (c1 > 0 && tid < c1 - 1) lds_st(&sU[(c1 - 1) & 1][tid * P], ldm<P>(U, g.psu, (long)(c1 - 1) * g.ldu + tid));
     __syncthreads();
     for (int i = c1 - 1; i >= 0; --i) {
         const int buf = i & 1;
+        // column i-1 (rows above i-1) for the next step, in flight during this one
+        V<P> unext = zero<P>();
+        const bool pre = i > 0 && tid < i - 1;
+        if (pre) unext = ldm<P>(U, g.psu, (long)(i - 1) * g.ldu + tid);
         // owner of row i in column j publishes x_ij
         if (j < c1 && j >= i && (i % RG) == rg) {
             const int qi = i / RG;
@@ -1180,9 +1186,11 @@ __global__ __launch_bounds__(kThreads) void k_invert(InvArgs g)
 #pragma unroll
             for (int q = 0; q < RPT; ++q) {
                 const int k = rg + q * RG;
-                if (k < i) r[q] = fma(r[q], neg(ldm<P>(U, g.psu, (long)i * g.ldu + k)), xv);
+                if (k < i) r[q] = fma(r[q], neg(lds_ld<P>(&sU[buf][k * P])), xv);
             }
         }
+        // sU[buf ^ 1] was last read in step i + 1, before this step's barrier
+        if (pre) lds_st(&sU[buf ^ 1][tid * P], unext);
     }
 }
 
@@ -1216,8 +1224,25 @@ __global__ __launch_bounds__(kThreads) void k_bs_upd(const double *Rc, long ldr,
     const int q = (tile + 3) / 4;
     const int cb = wid * q, ce = min(tile, cb + q);
     Acc<P> acc = acc_zero<P>();
-    if (row < rows)
-        for (int c = cb; c < ce; ++c) acc_fma_step(acc, ldm<P>(Rc, psr, (long)c * ldr + row), lds_ld<P>(&sx[c * P]), c - cb);
+    if (row < rows) {
+        // B columns of R per batch; the next batch's loads are issued before the current
+        // batch's multiply-adds, so the HBM latency overlaps the dependent accumulation
+        constexpr int B = 32 / P;
+        V<P> cur[B], nxt[B];
+        auto load = [&](V<P> (&u)[B], int c) __attribute__((always_inline)) {
+#pragma unroll
+            for (int k = 0; k < B; ++k) u[k] = (c + k < ce) ? ldm<P>(Rc, psr, (long)(c + k) * ldr + row) : zero<P>();
+        };
+        load(cur, cb);
+        for (int c = cb; c < ce; c += B) {
+            if (c + B < ce) load(nxt, c + B);
+#pragma unroll
+            for (int k = 0; k < B; ++k)
+                if (c + k < ce) acc_fma_step(acc, cur[k], lds_ld<P>(&sx[(c + k) * P]), c + k - cb);
+#pragma unroll
+            for (int k = 0; k < B; ++k) cur[k] = nxt[k];
+        }
+    }
     lds_st(&sp[wid][lane * P], acc_get(acc));
     __syncthreads();
     if (wid == 0 && row < rows) {
