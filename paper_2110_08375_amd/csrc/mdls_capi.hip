@@ -102,7 +102,10 @@ void timing_begin(hipStream_t s, void **ev)
 {
     std::lock_guard<std::mutex> lk(g_mu);
     hipEvent_t e = pool_get();
-    if (e) hipEventRecord(e, s);
+    if (e && hipEventRecord(e, s) != hipSuccess) {
+        g_pool.push_back(e);  // not recorded: the launch goes untimed
+        e = nullptr;
+    }
     *ev = (void *)e;
 }
 
@@ -111,7 +114,11 @@ void timing_end(hipStream_t s, void *ev, const char *name, int P, double work)
     std::lock_guard<std::mutex> lk(g_mu);
     hipEvent_t e = pool_get();
     if (!ev || !e) return;
-    hipEventRecord(e, s);
+    if (hipEventRecord(e, s) != hipSuccess) {
+        g_pool.push_back(e);
+        g_pool.push_back((hipEvent_t)ev);
+        return;
+    }
     g_rec.push_back(Timed{std::string(name), P, work, (hipEvent_t)ev, e});
 }
 }  // namespace mdls_impl
@@ -351,8 +358,7 @@ int mdls_batch_autotune(int p, int count, const double *A_src, const double *b_s
             best_ms = t;
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    if (hipEventDestroy(e0) != hipSuccess || hipEventDestroy(e1) != hipSuccess) rc = rc ? rc : MDLS_EHIP;
     return rc != 0 ? rc : best;
 }
 
@@ -404,13 +410,14 @@ int mdls_timing_enable(int on)
 int mdls_timing_reset(void)
 {
     std::lock_guard<std::mutex> lk(g_mu);
+    int rc = 0;
     for (auto &t : g_rec) {
-        hipEventSynchronize(t.b);
+        if (hipEventSynchronize(t.b) != hipSuccess) rc = MDLS_EHIP;
         g_pool.push_back(t.a);
         g_pool.push_back(t.b);
     }
     g_rec.clear();
-    return 0;
+    return rc;
 }
 
 int mdls_timing_query(const char *name, int p, double *total_ms, long *launches, double *md_fmas)

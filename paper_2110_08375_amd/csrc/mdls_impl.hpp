@@ -194,7 +194,7 @@ __device__ __forceinline__ int slot_scatter_index(int lane)
 //
 // When off = W the kernel first applies the previous panel's block reflector to its own
 // columns, C := C - Y' T'^T (Y'^T C) over the rows from the previous diagonal down (this is
-// the look-ahead: the rest of the trailing matrix is updated by the k_apply kernels
+// the look-ahead: the rest of the trailing matrix is updated by the k_apply_s/t/u kernels
 // concurrently).
 //
 // Column j of the panel, x = A(j:h, j) with x1 = a_jj, sigma = sum_{i>j} x_i^2, mu = ||x||:
@@ -1542,14 +1542,14 @@ void launch_apply(const Ctx<P> &cx, ApplyArgs aa, int grid_cap, hipStream_t st)
 
 // Householder QR of A (m x n) in narrow panels of W columns; B (nb columns, may be null)
 // receives Q^T B.  Panel l (l > 0) first applies panel l-1 to its own columns (k_panel with
-// off = W); apply(l) (the k_apply kernels) updates the columns from panel l+2 on, and B.  With
-// look-ahead (default; MDLS_LOOKAHEAD=0 turns it off) apply(l) runs on a side stream
-// concurrently with panel l+1:
+// off = W); apply(l) (k_apply_s, k_apply_t, k_apply_u) updates the columns from panel l+2 on,
+// and B.  With look-ahead (default; MDLS_LOOKAHEAD=0 turns it off) apply(l) runs on a side
+// stream concurrently with panel l+1:
 //   caller: panel(l) -> [wait apply(l-1)] -> panel(l+1) -> [wait apply(l)] -> panel(l+2) ...
 //   side:   [wait panel(l)] -> apply(l) -> [wait panel(l+1)] -> apply(l+1) ...
 // and its grid is capped so that CUs stay free for the panel's workgroups.
 template <int P>
-void qr_panels(const Ctx<P> &cx, int m, int n, double *A, long lda, long psa, double *B, long ldb, long psb, int nb)
+int qr_panels(const Ctx<P> &cx, int m, int n, double *A, long lda, long psa, double *B, long ldb, long psb, int nb)
 {
     constexpr int W = Cfg<P>::W;
     const PanelCfg cf = panel_cfg(P);
@@ -1583,7 +1583,8 @@ void qr_panels(const Ctx<P> &cx, int m, int n, double *A, long lda, long psa, do
         int G = (h + off + rows_per_wg - 1) / rows_per_wg;
         if (G < 1) G = 1;
         pa.G = G;
-        if (ss && l >= 2) hipStreamWaitEvent(cx.s, ss->ev_wide[l & 1], 0);  // apply(l-2) updated this panel
+        if (ss && l >= 2 && hipStreamWaitEvent(cx.s, ss->ev_wide[l & 1], 0) != hipSuccess)  // apply(l-2)
+            return MDLS_EHIP;
         launch_panel<P, W>(pa, cf, cx.s);
 
         // the update of everything right of the next panel, and of B
@@ -1606,18 +1607,19 @@ void qr_panels(const Ctx<P> &cx, int m, int n, double *A, long lda, long psa, do
         aa.psb = psb;
         aa.nb = B ? nb : 0;
         if (ss) {
-            hipEventRecord(ss->ev_panel, cx.s);
-            hipStreamWaitEvent(ss->q, ss->ev_panel, 0);
+            if (hipEventRecord(ss->ev_panel, cx.s) != hipSuccess ||
+                hipStreamWaitEvent(ss->q, ss->ev_panel, 0) != hipSuccess)
+                return MDLS_EHIP;
             launch_apply<P>(cx, aa, apply_grid_cap(P, h), ss->q);
-            hipEventRecord(ss->ev_wide[l & 1], ss->q);
+            if (hipEventRecord(ss->ev_wide[l & 1], ss->q) != hipSuccess) return MDLS_EHIP;
         } else {
             launch_apply<P>(cx, aa, 0, cx.s);
         }
     }
-    if (ss) {
-        hipStreamWaitEvent(cx.s, ss->ev_wide[(nleaves - 1) & 1], 0);
-        if (nleaves >= 2) hipStreamWaitEvent(cx.s, ss->ev_wide[nleaves & 1], 0);
-    }
+    if (ss && (hipStreamWaitEvent(cx.s, ss->ev_wide[(nleaves - 1) & 1], 0) != hipSuccess ||
+               (nleaves >= 2 && hipStreamWaitEvent(cx.s, ss->ev_wide[nleaves & 1], 0) != hipSuccess)))
+        return MDLS_EHIP;
+    return 0;
 }
 
 template <int P>
@@ -1673,7 +1675,7 @@ int solve_t(int m, int n, int tile, double *A, int lda, double *b, double *x, vo
 {
     Ctx<P> cx{(char *)ws, layout(P, m, n, tile), s};
     const long psa = (long)lda * n;
-    qr_panels<P>(cx, m, n, A, lda, psa, b, m, m, 1);
+    if (qr_panels<P>(cx, m, n, A, lda, psa, b, m, m, 1) != 0) return MDLS_EHIP;
     MDLS_LAUNCH("k_copy", P, 0, k_copy, dim3((n + 255) / 256), dim3(256), s, b, (long)m, cx.yw(), (long)n, n, P);
     backsub_tiles<P>(cx, n, tile, A, lda, psa, x, n, d_info);
     return hipGetLastError() == hipSuccess ? 0 : MDLS_EHIP;
@@ -1684,7 +1686,7 @@ int qr_t(int m, int n, int tile, double *A, int lda, double *T, int ldt, void *w
 {
     Ctx<P> cx{(char *)ws, layout(P, m, n, tile), s};
     const long psa = (long)lda * n;
-    qr_panels<P>(cx, m, n, A, lda, psa, nullptr, 0, 0, 0);
+    if (qr_panels<P>(cx, m, n, A, lda, psa, nullptr, 0, 0, 0) != 0) return MDLS_EHIP;
     if (T) {
         const int N = n / tile;
         double *G = cx.big();

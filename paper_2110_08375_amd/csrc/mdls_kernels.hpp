@@ -92,15 +92,6 @@ __device__ __forceinline__ V<P> wave_sum(V<P> v)
     return v;
 }
 
-// Butterfly sum over aligned groups of G lanes (G a power of two <= 64).
-template <int P, int G>
-__device__ __forceinline__ V<P> group_sum(V<P> v)
-{
-#pragma unroll
-    for (int m = G / 2; m >= 1; m >>= 1) v = add(v, shfl_xor_md(v, m));
-    return v;
-}
-
 // Coherent (agent-scope) scalar accesses for data exchanged between workgroups inside one
 // launch: they bypass the non-coherent caches of the other XCDs.
 __device__ __forceinline__ void st_coherent(double *p, double v)
