@@ -192,7 +192,8 @@ int mdls_wall_clock_khz(int *khz);
  * and its algorithmic multiple-double multiply-add count.  Host-side state shared by all
  * threads of the process; meant for benchmarks, not for concurrent production calls.
  *   mdls_timing_enable(on)    start (on != 0) or stop recording; returns 0.
- *   mdls_timing_reset()       wait for and discard all records; returns 0.
+ *   mdls_timing_reset()       wait for and discard all records; returns 0, or MDLS_EHIP if a
+ *                             recorded event could not be waited for.
  *   mdls_timing_query(name, p, &ms, &launches, &md_fmas)
  *                             waits for the recorded events and sums the launches of kernel
  *                             `name` ("" = all kernels) at precision p (0 = all); returns 0,
