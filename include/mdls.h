@@ -83,6 +83,20 @@ int mdls_apply_qt(int p, int m, int n, int tile, const double *A, int lda, const
                   hipStream_t stream);
 
 /*
+ * B := Q B (the tile blocks in reverse order: B := (I - Y_k T_k Y_k^T) B), and the explicit
+ * orthogonal factor the paper's Algorithm 2 forms (Section 3): mdls_form_q writes the first
+ * ncols (1 <= ncols <= m) columns of Q (m x m) into Q (P planes of ldq x ncols, ldq >= m).
+ * A and T as returned by mdls_qr with the same tile; n % tile == 0.  Negative status as for
+ * mdls_apply_qt (for mdls_form_q: -9 Q null, -10 ldq < m, -11 ncols, -12/-13 workspace).
+ */
+int mdls_apply_q(int p, int m, int n, int tile, const double *A, int lda, const double *T,
+                 int ldt, double *B, int ldb, int nrhs, void *ws, size_t ws_bytes,
+                 hipStream_t stream);
+int mdls_form_q(int p, int m, int n, int tile, const double *A, int lda, const double *T,
+                int ldt, double *Q, int ldq, int ncols, void *ws, size_t ws_bytes,
+                hipStream_t stream);
+
+/*
  * The paper's W factor (Section 3, eqs. for P_WY = I + W Y^T): W_k = -Y_k T_k for every
  * tile block, written to W (P planes of ldw x n, ldw >= m): block k occupies columns
  * k*tile.. and rows k*tile..m-1; rows above are set to zero.

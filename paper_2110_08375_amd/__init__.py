@@ -10,6 +10,7 @@ from .mdls import (  # noqa: F401
     MDLS_OD,
     MDLS_QD,
     BatchDesc,
+    apply_q,
     apply_qt,
     backsub,
     batch_autotune,
@@ -17,6 +18,7 @@ from .mdls import (  # noqa: F401
     batch_plan,
     batch_variants,
     batch_workspace,
+    form_q,
     form_w,
     lib,
     max_rows,

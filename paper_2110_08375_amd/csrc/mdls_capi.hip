@@ -152,6 +152,16 @@ struct ApplyF {
     static int run(A... a) { return apply_qt_t<P>(a...); }
 };
 template <int P>
+struct ApplyQF {
+    template <typename... A>
+    static int run(A... a) { return apply_q_t<P>(a...); }
+};
+template <int P>
+struct FormQF {
+    template <typename... A>
+    static int run(A... a) { return form_q_t<P>(a...); }
+};
+template <int P>
 struct FormWF {
     template <typename... A>
     static int run(A... a) { return form_w_t<P>(a...); }
@@ -214,6 +224,45 @@ int mdls_apply_qt(int p, int m, int n, int tile, const double *A, int lda, const
     if (ws_bytes < mdls_workspace_bytes(p, m, n, tile)) return -13;
     if (nrhs == 0) return 0;
     return dispatch<ApplyF>(p, m, n, tile, A, lda, T, ldt, B, ldb, nrhs, ws, stream);
+}
+
+int mdls_apply_q(int p, int m, int n, int tile, const double *A, int lda, const double *T, int ldt, double *B,
+                 int ldb, int nrhs, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    if (!valid_p(p)) return -1;
+    if (m < 1) return -2;
+    if (n < 1 || n > m) return -3;
+    if (!valid_tile(tile) || n % tile != 0) return -4;
+    if (!A) return -5;
+    if (lda < m) return -6;
+    if (!T) return -7;
+    if (ldt < tile) return -8;
+    if (!B && nrhs > 0) return -9;
+    if (ldb < m) return -10;
+    if (nrhs < 0) return -11;
+    if (!ws) return -12;
+    if (ws_bytes < mdls_workspace_bytes(p, m, n, tile)) return -13;
+    if (nrhs == 0) return 0;
+    return dispatch<ApplyQF>(p, m, n, tile, A, lda, T, ldt, B, ldb, nrhs, ws, stream);
+}
+
+int mdls_form_q(int p, int m, int n, int tile, const double *A, int lda, const double *T, int ldt, double *Q, int ldq,
+                int ncols, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    if (!valid_p(p)) return -1;
+    if (m < 1) return -2;
+    if (n < 1 || n > m) return -3;
+    if (!valid_tile(tile) || n % tile != 0) return -4;
+    if (!A) return -5;
+    if (lda < m) return -6;
+    if (!T) return -7;
+    if (ldt < tile) return -8;
+    if (!Q) return -9;
+    if (ldq < m) return -10;
+    if (ncols < 1 || ncols > m) return -11;
+    if (!ws) return -12;
+    if (ws_bytes < mdls_workspace_bytes(p, m, n, tile)) return -13;
+    return dispatch<FormQF>(p, m, n, tile, A, lda, T, ldt, Q, ldq, ncols, ws, stream);
 }
 
 int mdls_form_w(int p, int m, int n, int tile, const double *A, int lda, const double *T, int ldt, double *W, int ldw,

@@ -1328,6 +1328,30 @@ __global__ __launch_bounds__(kThreads) void k_trmm_t(const double *T, long ldt, 
     stm(U, sps, (long)c * tile + i, acc_get(acc));
 }
 
+// U(i, c) = sum_{l>=i} T(i, l) S(l, c) (T upper triangular, applied without transposition)
+template <int P>
+__global__ __launch_bounds__(kThreads) void k_trmm_n(const double *T, long ldt, long tps, const double *S, long sps,
+                                                    double *U, int tile, int nrhs)
+{
+    const int i = blockIdx.x * kThreads + threadIdx.x, c = blockIdx.y;
+    if (i >= tile || c >= nrhs) return;
+    Acc<P> acc = acc_zero<P>();
+    for (int l = i; l < tile; ++l)
+        acc_fma_step(acc, ldm<P>(T, tps, (long)l * ldt + i), ldm<P>(S, sps, (long)c * tile + l), l - i);
+    stm(U, sps, (long)c * tile + i, acc_get(acc));
+}
+
+namespace {
+// B(i, c) = 1 if i == c else 0, for i < rows and c < cols (P planes, ld ldb)
+__global__ void k_identity(double *B, long ldb, long bps, int rows, int cols, int P)
+{
+    const long r = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
+    if (r >= rows || c >= cols) return;
+    for (int k = 0; k < P; ++k) B[k * bps + (long)c * ldb + r] = (k == 0 && r == c) ? 1.0 : 0.0;
+}
+}  // namespace
+
 // B(kt + r, c) -= sum_l Y_k(r, l) U(l, c)
 template <int P>
 __global__ __launch_bounds__(kThreads) void k_nn_sub(const double *Y, long lda, long ps, int h, int tile, const double *U,
@@ -1740,6 +1764,47 @@ int apply_qt_t(int m, int n, int tile, const double *A, int lda, const double *T
     return hipGetLastError() == hipSuccess ? 0 : MDLS_EHIP;
 }
 
+// B := Q B = Q_0 Q_1 ... Q_{N-1} B with Q_k = I - Y_k T_k Y_k^T: the tiles in reverse order,
+// B -= Y_k T_k (Y_k^T B) (the paper forms Q itself, Algorithm 2; with B = I this is that Q).
+template <int P>
+int apply_q_t(int m, int n, int tile, const double *A, int lda, const double *T, int ldt, double *B, int ldb, int nrhs,
+              void *ws, hipStream_t s)
+{
+    Ctx<P> cx{(char *)ws, layout(P, m, n, tile), s};
+    const long psa = (long)lda * n, tps = (long)ldt * n, bps = (long)ldb * nrhs;
+    double *S = cx.big();
+    double *U = S + (size_t)P * tile * 64;
+    const long sps = (long)tile * 64;
+    const int N = n / tile;
+    for (int c0 = 0; c0 < nrhs; c0 += 64) {
+        const int nc = (nrhs - c0 < 64) ? nrhs - c0 : 64;
+        double *Bc = B + (long)c0 * ldb;
+        for (int k = N - 1; k >= 0; --k) {
+            const long kt = (long)k * tile;
+            const double *Y = A + kt * lda + kt;
+            const int h = m - (int)kt;
+            MDLS_LAUNCH("k_tn", P, (double)h * tile * nc, (k_tn<P>), dim3((tile + 3) / 4, nc), dim3(kThreads), s, Y,
+                        (long)lda, psa, h, tile, Bc + kt, (long)ldb, bps, nc, S, sps);
+            MDLS_LAUNCH("k_trmm_n", P, 0.5 * tile * tile * nc, (k_trmm_n<P>), dim3((tile + kThreads - 1) / kThreads, nc),
+                        dim3(kThreads), s, T + kt * ldt, (long)ldt, tps, S, sps, U, tile, nc);
+            MDLS_LAUNCH("k_nn_sub", P, (double)h * tile * nc, (k_nn_sub<P>), dim3((h + kThreads - 1) / kThreads, nc),
+                        dim3(kThreads), s, Y, (long)lda, psa, h, tile, U, sps, Bc + kt, (long)ldb, bps);
+        }
+    }
+    return hipGetLastError() == hipSuccess ? 0 : MDLS_EHIP;
+}
+
+// Q(:, 0:ncols) := the first ncols columns of Q (m x m orthogonal factor), ld ldq
+template <int P>
+int form_q_t(int m, int n, int tile, const double *A, int lda, const double *T, int ldt, double *Q, int ldq, int ncols,
+             void *ws, hipStream_t s)
+{
+    const long qps = (long)ldq * ncols;
+    MDLS_LAUNCH("k_identity", P, 0, k_identity, dim3((m + 255) / 256, ncols), dim3(256), s, Q, (long)ldq, qps, m, ncols,
+                P);
+    return apply_q_t<P>(m, n, tile, A, lda, T, ldt, Q, ldq, ncols, ws, s);
+}
+
 template <int P>
 int form_w_t(int m, int n, int tile, const double *A, int lda, const double *T, int ldt, double *W, int ldw,
              hipStream_t s)
@@ -1946,6 +2011,10 @@ int refine_t(int m, int n, int tile, const double *A, int lda, const double *b, 
                                  void *, hipStream_t);                                                         \
     X template int form_w_t<P>(int, int, int, const double *, int, const double *, int, double *, int,         \
                                hipStream_t);                                                                   \
-    X template int backsub_t<P>(int, int, const double *, int, double *, void *, int *, hipStream_t);
+    X template int backsub_t<P>(int, int, const double *, int, double *, void *, int *, hipStream_t);          \
+    X template int apply_q_t<P>(int, int, int, const double *, int, const double *, int, double *, int, int,    \
+                                void *, hipStream_t);                                                          \
+    X template int form_q_t<P>(int, int, int, const double *, int, const double *, int, double *, int, int,     \
+                               void *, hipStream_t);
 
 }  // namespace mdls_impl

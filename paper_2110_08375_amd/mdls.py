@@ -22,7 +22,7 @@ EXPORTS = ("mdls_max_rows", "mdls_workspace_bytes", "mdls_qr", "mdls_apply_qt", 
            "mdls_backsub", "mdls_solve", "mdls_status_string", "mdls_timing_enable", "mdls_timing_reset",
            "mdls_timing_query", "mdls_timing_kernels", "mdls_batch_workspace_bytes", "mdls_batch_plan",
            "mdls_solve_batched", "mdls_batch_variants", "mdls_batch_autotune", "mdls_wall_clock_khz",
-           "mdls_refined_workspace_bytes", "mdls_solve_refined")
+           "mdls_refined_workspace_bytes", "mdls_solve_refined", "mdls_apply_q", "mdls_form_q")
 
 
 class BatchDesc(ctypes.Structure):
@@ -53,6 +53,8 @@ def lib():
         L.mdls_qr.argtypes = [i, i, i, i, vp, i, vp, i, vp, sz, vp]
         L.mdls_apply_qt.argtypes = [i, i, i, i, vp, i, vp, i, vp, i, i, vp, sz, vp]
         L.mdls_form_w.argtypes = [i, i, i, i, vp, i, vp, i, vp, i, vp]
+        L.mdls_apply_q.argtypes = [i, i, i, i, vp, i, vp, i, vp, i, i, vp, sz, vp]
+        L.mdls_form_q.argtypes = [i, i, i, i, vp, i, vp, i, vp, i, i, vp, sz, vp]
         L.mdls_backsub.argtypes = [i, i, i, vp, i, vp, vp, sz, vp, vp]
         L.mdls_solve.argtypes = [i, i, i, i, vp, i, vp, vp, vp, sz, vp, vp]
         L.mdls_status_string.argtypes = [i]
@@ -73,10 +75,10 @@ def lib():
         L.mdls_refined_workspace_bytes.argtypes = [i, i, i, i]
         L.mdls_refined_workspace_bytes.restype = sz
         L.mdls_solve_refined.argtypes = [i, i, i, i, vp, i, vp, vp, i, vp, vp, sz, vp, vp, vp]
-        for f in ("mdls_qr", "mdls_apply_qt", "mdls_form_w", "mdls_backsub", "mdls_solve", "mdls_timing_enable",
-                  "mdls_timing_reset", "mdls_timing_query", "mdls_timing_kernels", "mdls_batch_plan",
-                  "mdls_solve_batched", "mdls_batch_variants", "mdls_batch_autotune", "mdls_wall_clock_khz",
-           "mdls_refined_workspace_bytes", "mdls_solve_refined"):
+        for f in ("mdls_qr", "mdls_apply_qt", "mdls_apply_q", "mdls_form_q", "mdls_form_w", "mdls_backsub",
+                  "mdls_solve", "mdls_timing_enable", "mdls_timing_reset", "mdls_timing_query", "mdls_timing_kernels",
+                  "mdls_batch_plan", "mdls_solve_batched", "mdls_batch_variants", "mdls_batch_autotune",
+                  "mdls_wall_clock_khz", "mdls_solve_refined"):
             getattr(L, f).restype = i
         _lib = L
     return _lib
@@ -160,6 +162,32 @@ def apply_qt(p: int, A, T, B, tile: int, ws=None):
                              ws.numel(), _stream())
     _check(rc, "mdls_apply_qt")
     return B
+
+
+def apply_q(p: int, A, T, B, tile: int, ws=None):
+    """B (P, nrhs, m) := Q B, in place."""
+    m, n = _mat(A, p, "A")
+    ldt, _ = _mat(T, p, "T")
+    ldb, nrhs = _mat(B, p, "B")
+    if ws is None:
+        ws = workspace(p, m, n, tile, A.device)
+    rc = lib().mdls_apply_q(p, m, n, tile, _ptr(A), m, _ptr(T), ldt, _ptr(B), ldb, nrhs, _ptr(ws), ws.numel(),
+                            _stream())
+    _check(rc, "mdls_apply_q")
+    return B
+
+
+def form_q(p: int, A, T, tile: int, Q, ws=None):
+    """Q (P, ncols, m) := the first ncols columns of the explicit orthogonal factor."""
+    m, n = _mat(A, p, "A")
+    ldt, _ = _mat(T, p, "T")
+    ldq, ncols = _mat(Q, p, "Q")
+    if ws is None:
+        ws = workspace(p, m, n, tile, A.device)
+    rc = lib().mdls_form_q(p, m, n, tile, _ptr(A), m, _ptr(T), ldt, _ptr(Q), ldq, ncols, _ptr(ws), ws.numel(),
+                           _stream())
+    _check(rc, "mdls_form_q")
+    return Q
 
 
 def form_w(p: int, A, T, tile: int, W):

@@ -131,3 +131,15 @@ def test_refined_entry_point_errors(L):
     assert f(8, 64, 32, 16, d, 64, d, d, 4, None, d, ws, d, d, None) == -10
     assert f(8, 64, 32, 16, d, 64, d, d, 4, d, d, ws - 1, d, d, None) == -12
     assert f(8, 64, 32, 16, d, 64, d, d, 4, d, d, ws, d, None, None) == -14
+
+
+def test_explicit_q_entry_point_errors(L):
+    d = ctypes.c_void_p(16)
+    ws = L.mdls_workspace_bytes(4, 64, 32, 16)
+    assert L.mdls_apply_q(4, 64, 32, 12, d, 64, d, 16, d, 64, 1, d, ws, None) == -4
+    assert L.mdls_apply_q(4, 64, 32, 16, d, 64, None, 16, d, 64, 1, d, ws, None) == -7
+    assert L.mdls_apply_q(4, 64, 32, 16, d, 64, d, 16, d, 64, -1, d, ws, None) == -11
+    assert L.mdls_form_q(4, 64, 32, 16, d, 64, d, 16, None, 64, 64, d, ws, None) == -9
+    assert L.mdls_form_q(4, 64, 32, 16, d, 64, d, 16, d, 63, 64, d, ws, None) == -10
+    assert L.mdls_form_q(4, 64, 32, 16, d, 64, d, 16, d, 64, 65, d, ws, None) == -11
+    assert L.mdls_form_q(4, 64, 32, 16, d, 64, d, 16, d, 64, 64, d, ws - 1, None) == -13

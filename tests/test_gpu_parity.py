@@ -300,3 +300,42 @@ def test_solve_graph_replay(M):
         torch.cuda.synchronize()
         assert np.array_equal(x.cpu().numpy(), ref), rep
         assert int(info.item()) == 0
+
+
+@pytest.mark.parametrize("P", (2, 4, 8))
+def test_form_q_matches_oracle(M, orc, P):
+    """The explicit orthogonal factor (the paper's Algorithm 2 forms Q) against the oracle's
+    backward accumulation of its own reflectors, column by column."""
+    m, n, tile = 40, 16, 8
+    print("case form_q P=%d" % P, flush=True)
+    A = mdgen.md_uniform(P, m, n, 91, mdgen.STREAM_A)
+    Fo, beta = orc.qr(A)
+    Qo = orc.explicit_q(Fo, beta)
+    Ag = to_gpu(A)
+    T = torch.zeros((P, n, tile), dtype=torch.float64, device=dev())
+    M.qr(P, Ag, tile, T=T)
+    Q = torch.zeros((P, m, m), dtype=torch.float64, device=dev())
+    M.form_q(P, Ag, T, tile, Q)
+    torch.cuda.synchronize()
+    Qn = Q.cpu().numpy()
+    k = kappa(A)
+    for c in range(m):
+        assert md_err(Qn[:, c, :], Qo[:, c, :]) <= TOL[P] * max(1, k) * 10, c
+
+
+@pytest.mark.parametrize("P", (2, 8))
+def test_apply_q_inverts_apply_qt(M, P):
+    """Q (Q^T B) = B on random right-hand sides (m = 300, n = 128, tile 32)."""
+    m, n, tile = 300, 128, 32
+    A = mdgen.md_uniform(P, m, n, 92, mdgen.STREAM_A)
+    B = mdgen.md_uniform(P, m, 5, 93, mdgen.STREAM_B)
+    Ag = to_gpu(A)
+    T = torch.zeros((P, n, tile), dtype=torch.float64, device=dev())
+    M.qr(P, Ag, tile, T=T)
+    Bg = to_gpu(B)
+    M.apply_qt(P, Ag, T, Bg, tile)
+    M.apply_q(P, Ag, T, Bg, tile)
+    torch.cuda.synchronize()
+    Bn = Bg.cpu().numpy()
+    for c in range(5):
+        assert md_err(Bn[:, c, :], B[:, c, :]) <= TOL[P] * 100, c
