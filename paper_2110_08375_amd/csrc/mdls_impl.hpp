@@ -69,11 +69,13 @@ __device__ __forceinline__ V<P> y_entry(const double *Y, long ldy, long psy, lon
 __device__ inline void grid_sync(unsigned *ctr, unsigned target, int *err)
 {
     const int lane = threadIdx.x & 63;
+    // the fence before the relaxed arrival releases this workgroup's stores; the relaxed
+    // polls need no cache invalidation each, the fence after them acquires the others' stores
     __threadfence();
     if (lane == 0) {
-        __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         unsigned spins = 0;
-        while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             __builtin_amdgcn_s_sleep(1);
             if (++spins > (1u << 22)) {
                 __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
