@@ -46,6 +46,7 @@ STREAM_B = 3
 STREAM_DIAG = 4
 STREAM_U = 7
 STREAM_V = 8
+STREAM_IM = 16  # added to a stream number for the imaginary parts of complex data
 
 
 def _mix_int(z: int) -> int:
@@ -272,6 +273,30 @@ def ls_problem(P: int, m: int, n: int, seed: int, ones_solution: bool = False, d
     A = md_uniform(P, m, n, seed, STREAM_A, device=device)
     x = md_ones(P, n, device=device) if ones_solution else md_vector(P, n, seed, STREAM_X, device=device)
     return A, x
+
+
+def cmd_uniform(P: int, rows: int, cols: int, seed: int, stream: int, device=None):
+    """Complex md matrix, shape (2, P, cols, rows): real parts drawn from ``stream``,
+    imaginary parts from ``stream + STREAM_IM`` (real and imaginary parts in separate
+    arrays, the paper's staging of complex data at the end of Section 2)."""
+    re = md_uniform(P, rows, cols, seed, stream, device=device)
+    im = md_uniform(P, rows, cols, seed, stream + STREAM_IM, device=device)
+    if device is None:
+        return np.stack([re, im])
+    import torch
+
+    return torch.stack([re, im]).contiguous()
+
+
+def cmd_vector(P: int, n: int, seed: int, stream: int, device=None):
+    """Complex md vector, shape (2, P, n)."""
+    return cmd_uniform(P, n, 1, seed, stream, device=device).reshape(2, P, n)
+
+
+def cls_problem(P: int, m: int, n: int, seed: int, device=None):
+    """Complex A (2, P, n, m) and x_true (2, P, n) for a least-squares test problem."""
+    return (cmd_uniform(P, m, n, seed, STREAM_A, device=device),
+            cmd_vector(P, n, seed, STREAM_X, device=device))
 
 
 def batch_shapes(count: int, seed: int, m_lo: int = 32, m_hi: int = 512, n_lo: int = 16):

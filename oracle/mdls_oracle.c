@@ -32,6 +32,11 @@
  * planes of doubles, most significant first; each plane is column-major with leading
  * dimension ld; plane k starts ps doubles after plane k-1.  Vectors: P planes of stride vs.
  *
+ * Complex data (the paper's complex double double QR, Section 4 Table 5): the same unblocked
+ * QR, Q^H b and back substitution with complex multiple doubles (real and imaginary parts in
+ * separate limb planes) and the Hermitian transpose in place of the transpose (Section 3);
+ * the complex Householder vector is described above orc_cqr.
+ *
  * Threading: OpenMP over independent columns (trailing columns, right-hand sides, rows
  * of a matrix-vector product).  Results do not depend on the thread count.
  */
@@ -592,6 +597,358 @@ int orc_matvec(int trans, int Pa, int Px, int Pc, int Py, int rows, int cols, co
         xacc_round(acc, Py, out);
         stm(Py, y, ys, o, out);
         free(acc);
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ complex multiple doubles */
+/*
+ * A complex multiple double is a pair (re, im) of P-limb numbers.  A complex matrix is 2P
+ * planes: the P limb planes of the real parts, then the P limb planes of the imaginary parts,
+ * every plane with the same stride ps (the paper keeps real and imaginary parts in separate
+ * arrays, end of Section 2).  On complex data the transpose of Algorithm 2 becomes the
+ * Hermitian transpose (Section 3).
+ *
+ * Householder vector of a complex column x (length L, x1 = |x1| e^{i theta}; theta = 0 when
+ * x1 = 0): sigma = sum_{i>1} |x_i|^2; if sigma = 0 the reflector is the identity (beta = 0,
+ * R_jj = x1 kept).  Otherwise mu = sqrt(|x1|^2 + sigma), and Golub-Van Loan 5.1.1 is applied
+ * to the modulus |x1| and rotated by the phase of x1: nu = |x1| - mu computed as
+ * -sigma/(|x1| + mu) when |x1| > 0 (else nu = -mu), v1 = e^{i theta} nu, beta = 2 nu^2 /
+ * (sigma + nu^2), v = x / v1.  Then H = I - beta v v^H is Hermitian and unitary and
+ * H x = e^{i theta} mu e_1, so R_jj = e^{i theta} mu; on real data with x1 > 0 this is the real
+ * reflector.
+ */
+typedef struct {
+    double re[ORC_MAXP], im[ORC_MAXP];
+} cmd;
+
+static inline void cld(int P, const double *X, long ps, long off, cmd *v)
+{
+    ldm(P, X, ps, off, v->re);
+    ldm(P, X + (long)P * ps, ps, off, v->im);
+}
+
+static inline void cst(int P, double *X, long ps, long off, const cmd *v)
+{
+    stm(P, X, ps, off, v->re);
+    stm(P, X + (long)P * ps, ps, off, v->im);
+}
+
+static int cmd_is_zero(int P, const cmd *a) { return md_is_zero(P, a->re) && md_is_zero(P, a->im); }
+
+/* r = op(a) * b with op(a) = a or conj(a); each part summed exactly, then truncated */
+static void cmd_mul_x(int P, const cmd *a, int conj_a, const cmd *b, cmd *r)
+{
+    const double sa = conj_a ? -1.0 : 1.0;
+    cmd t;
+    xacc x;
+    xacc_init(&x);
+    xacc_add_prod(&x, P, a->re, P, b->re, 1.0);
+    xacc_add_prod(&x, P, a->im, P, b->im, -sa);
+    xacc_round(&x, P, t.re);
+    xacc_init(&x);
+    xacc_add_prod(&x, P, a->re, P, b->im, 1.0);
+    xacc_add_prod(&x, P, a->im, P, b->re, sa);
+    xacc_round(&x, P, t.im);
+    *r = t;
+}
+
+static void cmd_add(int P, const cmd *a, const cmd *b, cmd *r)
+{
+    orc_md_add(P, a->re, b->re, r->re);
+    orc_md_add(P, a->im, b->im, r->im);
+}
+
+static void cmd_sub(int P, const cmd *a, const cmd *b, cmd *r)
+{
+    orc_md_sub(P, a->re, b->re, r->re);
+    orc_md_sub(P, a->im, b->im, r->im);
+}
+
+/* |a|^2, summed exactly, then truncated */
+static void cmd_abs2(int P, const cmd *a, double *r)
+{
+    xacc x;
+    xacc_init(&x);
+    xacc_add_prod(&x, P, a->re, P, a->re, 1.0);
+    xacc_add_prod(&x, P, a->im, P, a->im, 1.0);
+    xacc_round(&x, P, r);
+}
+
+/* a * s for a real multiple double s */
+static void cmd_scale(int P, const cmd *a, const double *s, cmd *r)
+{
+    cmd t;
+    orc_md_mul(P, a->re, s, t.re);
+    orc_md_mul(P, a->im, s, t.im);
+    *r = t;
+}
+
+/* a / b = (a conj(b)) / |b|^2 */
+static void cmd_div(int P, const cmd *a, const cmd *b, cmd *r)
+{
+    double d[ORC_MAXP];
+    cmd n;
+    cmd_abs2(P, b, d);
+    cmd_mul_x(P, b, 1, a, &n);  /* conj(b) a */
+    orc_md_div(P, n.re, d, r->re);
+    orc_md_div(P, n.im, d, r->im);
+}
+
+/* scalar entry points for tests: a, b, r hold 2P doubles (P real limbs, then P imaginary) */
+void orc_cmd_mul(int P, const double *a, const double *b, double *r)
+{
+    cmd x, y, z;
+    memcpy(x.re, a, sizeof(double) * P);
+    memcpy(x.im, a + P, sizeof(double) * P);
+    memcpy(y.re, b, sizeof(double) * P);
+    memcpy(y.im, b + P, sizeof(double) * P);
+    cmd_mul_x(P, &x, 0, &y, &z);
+    memcpy(r, z.re, sizeof(double) * P);
+    memcpy(r + P, z.im, sizeof(double) * P);
+}
+
+void orc_cmd_div(int P, const double *a, const double *b, double *r)
+{
+    cmd x, y, z;
+    memcpy(x.re, a, sizeof(double) * P);
+    memcpy(x.im, a + P, sizeof(double) * P);
+    memcpy(y.re, b, sizeof(double) * P);
+    memcpy(y.im, b + P, sizeof(double) * P);
+    cmd_div(P, &x, &y, &z);
+    memcpy(r, z.re, sizeof(double) * P);
+    memcpy(r + P, z.im, sizeof(double) * P);
+}
+
+/* B(j:m, c) := H B(j:m, c) for c in [c0, c1), H = I - beta v v^H with v = (1, A(j+1:m, j)) */
+static void capply_reflector(int P, int m, int j, const double *A, int lda, long psa, const double *bt, double *B,
+                             int ldb, long psb, int c0, int c1)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int c = c0; c < c1; c++) {
+        cmd w, a, v, p, t;
+        cld(P, B, psb, AT(j, c, ldb), &w); /* v_j = 1 */
+        for (int i = j + 1; i < m; i++) {
+            cld(P, A, psa, AT(i, j, lda), &v);
+            cld(P, B, psb, AT(i, c, ldb), &a);
+            cmd_mul_x(P, &v, 1, &a, &p); /* conj(v_i) a_i */
+            cmd_add(P, &w, &p, &w);
+        }
+        cmd_scale(P, &w, bt, &t); /* t = beta v^H b */
+        cld(P, B, psb, AT(j, c, ldb), &a);
+        cmd_sub(P, &a, &t, &a);
+        cst(P, B, psb, AT(j, c, ldb), &a);
+        for (int i = j + 1; i < m; i++) {
+            cld(P, A, psa, AT(i, j, lda), &v);
+            cld(P, B, psb, AT(i, c, ldb), &a);
+            cmd_mul_x(P, &v, 0, &t, &p);
+            cmd_sub(P, &a, &p, &a);
+            cst(P, B, psb, AT(i, c, ldb), &a);
+        }
+    }
+}
+
+/*
+ * Unblocked complex Householder QR of the m x n matrix A (m >= n), in place: R in the upper
+ * triangle, v_j below the diagonal of column j (unit first entry implicit), beta (P planes of
+ * stride n, real).  tally counts real multiple-double operations (a complex product is 4
+ * multiplications and 2 additions, a complex sum 2 additions, |z|^2 2 multiplications and
+ * 1 addition, a complex quotient 6 multiplications, 3 additions and 2 divisions).
+ */
+int orc_cqr(int P, int m, int n, double *A, int lda, long ps, double *beta, long *tally, int nthreads)
+{
+    if (!valid_p(P) || m < n || n < 0 || lda < m)
+        return -1;
+    set_threads(nthreads);
+    for (int j = 0; j < n; j++) {
+        double sig[ORC_MAXP], t1[ORC_MAXP], t2[ORC_MAXP], a2[ORC_MAXP], mu[ORC_MAXP], rho[ORC_MAXP];
+        double nu[ORC_MAXP], bt[ORC_MAXP];
+        cmd alpha, ph, v1, x, r;
+        long L = m - j;
+        memset(sig, 0, sizeof(sig));
+        for (int i = j + 1; i < m; i++) {
+            cld(P, A, ps, AT(i, j, lda), &x);
+            cmd_abs2(P, &x, t1);
+            orc_md_add(P, sig, t1, sig);
+        }
+        tally_add(tally, 2 * (L - 1), 2 * (L - 1), 0, 0);
+        cld(P, A, ps, AT(j, j, lda), &alpha);
+        if (md_is_zero(P, sig)) {
+            memset(bt, 0, sizeof(bt));
+            stm(P, beta, n, j, bt);
+            continue;
+        }
+        cmd_abs2(P, &alpha, a2);
+        orc_md_add(P, a2, sig, t1);
+        orc_md_sqrt(P, t1, mu);
+        orc_md_sqrt(P, a2, rho);
+        tally_add(tally, 2, 2, 0, 2);
+        memset(&ph, 0, sizeof(ph));
+        if (md_is_zero(P, rho)) {
+            ph.re[0] = 1.0;
+            md_neg(P, mu, nu);
+        } else {
+            orc_md_div(P, alpha.re, rho, ph.re);
+            orc_md_div(P, alpha.im, rho, ph.im);
+            orc_md_add(P, rho, mu, t1);
+            orc_md_div(P, sig, t1, t2);
+            md_neg(P, t2, nu);
+            tally_add(tally, 1, 0, 3, 0);
+        }
+        cmd_scale(P, &ph, nu, &v1);
+        orc_md_mul(P, nu, nu, t1);  /* nu^2 */
+        orc_md_add(P, sig, t1, t2); /* sigma + nu^2 */
+        for (int k = 0; k < P; k++)
+            t1[k] *= 2.0; /* exact */
+        orc_md_div(P, t1, t2, bt);
+        tally_add(tally, 1, 3, 1, 0);
+        stm(P, beta, n, j, bt);
+        for (int i = j + 1; i < m; i++) {
+            cld(P, A, ps, AT(i, j, lda), &x);
+            cmd_div(P, &x, &v1, &r);
+            cst(P, A, ps, AT(i, j, lda), &r);
+        }
+        tally_add(tally, 3 * (L - 1), 6 * (L - 1), 2 * (L - 1), 0);
+        cmd_scale(P, &ph, mu, &r);
+        cst(P, A, ps, AT(j, j, lda), &r);
+        tally_add(tally, 0, 2, 0, 0);
+        capply_reflector(P, m, j, A, lda, ps, bt, A, lda, ps, j + 1, n);
+        /* per column: L-1 conj products and sums, 1 scale, 1 sum, L-1 products and sums */
+        tally_add(tally, (long)(n - j - 1) * (8 * (L - 1) + 2), (long)(n - j - 1) * (8 * (L - 1) + 2), 0, 0);
+    }
+    return 0;
+}
+
+/* B := Q^H B = H_{n-1} ... H_0 B for the m x nrhs complex matrix B */
+int orc_capply_qh(int P, int m, int n, const double *A, int lda, long psa, const double *beta, double *B, int ldb,
+                  long psb, int nrhs, long *tally, int nthreads)
+{
+    if (!valid_p(P) || m < n || lda < m || ldb < m || nrhs < 0)
+        return -1;
+    set_threads(nthreads);
+    for (int j = 0; j < n; j++) {
+        double bt[ORC_MAXP];
+        ldm(P, beta, n, j, bt);
+        if (md_is_zero(P, bt))
+            continue;
+        capply_reflector(P, m, j, A, lda, psa, bt, B, ldb, psb, 0, nrhs);
+        tally_add(tally, (long)nrhs * (8 * (m - j - 1) + 2), (long)nrhs * (8 * (m - j - 1) + 2), 0, 0);
+    }
+    return 0;
+}
+
+/* Solve R x = y (complex, leading n x n upper triangle), rows n-1 down to 0, ascending k in
+ * each row sum.  info = smallest 1-based i with R_ii == 0 (then x is not computed). */
+int orc_cbacksub(int P, int n, const double *R, int ldr, long psr, const double *y, long ys, double *x, long xs,
+                 int *info, long *tally)
+{
+    cmd d, s, r, xk, p;
+    if (!valid_p(P) || n < 0 || ldr < n)
+        return -1;
+    *info = 0;
+    for (int i = 0; i < n; i++) {
+        cld(P, R, psr, AT(i, i, ldr), &d);
+        if (cmd_is_zero(P, &d)) {
+            *info = i + 1;
+            return 0;
+        }
+    }
+    for (int i = n - 1; i >= 0; i--) {
+        cld(P, y, ys, i, &s);
+        for (int k = i + 1; k < n; k++) {
+            cld(P, R, psr, AT(i, k, ldr), &r);
+            cld(P, x, xs, k, &xk);
+            cmd_mul_x(P, &r, 0, &xk, &p);
+            cmd_sub(P, &s, &p, &s);
+        }
+        cld(P, R, psr, AT(i, i, ldr), &d);
+        cmd_div(P, &s, &d, &p);
+        cst(P, x, xs, i, &p);
+    }
+    tally_add(tally, (long)n * (n - 1) / 2 * 4 + 3L * n, (long)n * (n - 1) / 2 * 4 + 6L * n, 2L * n, 0);
+    return 0;
+}
+
+/* Complex least squares: QR of A (in place), b := Q^H b (in place), x from R x = b(0:n). */
+int orc_clstsq(int P, int m, int n, double *A, int lda, long psa, double *b, long bs, double *x, long xs,
+               double *beta, int *info, long *tally, int nthreads)
+{
+    int rc = orc_cqr(P, m, n, A, lda, psa, beta, tally, nthreads);
+    if (rc)
+        return rc;
+    rc = orc_capply_qh(P, m, n, A, lda, psa, beta, b, m, bs, 1, tally, nthreads);
+    if (rc)
+        return rc;
+    return orc_cbacksub(P, n, A, lda, psa, b, bs, x, xs, info, tally);
+}
+
+/* Explicit m x m unitary Q = H_0 H_1 ... H_{n-1}, by backward accumulation onto I. */
+int orc_cexplicit_q(int P, int m, int n, const double *A, int lda, long psa, const double *beta, double *Q, int ldq,
+                    long psq, int nthreads)
+{
+    if (!valid_p(P) || m < n || lda < m || ldq < m)
+        return -1;
+    set_threads(nthreads);
+    for (int k = 0; k < 2 * P; k++)
+        for (int c = 0; c < m; c++)
+            for (int i = 0; i < m; i++)
+                Q[(long)k * psq + AT(i, c, ldq)] = (k == 0 && i == c) ? 1.0 : 0.0;
+    for (int j = n - 1; j >= 0; j--) {
+        double bt[ORC_MAXP];
+        ldm(P, beta, n, j, bt);
+        if (md_is_zero(P, bt))
+            continue;
+        capply_reflector(P, m, j, A, lda, psa, bt, Q, ldq, psq, j, m);
+    }
+    return 0;
+}
+
+/*
+ * Complex y := op(A) x  or  y := c - op(A) x  (when c != NULL), op(A) = A (trans == 0) or
+ * A^H (trans != 0); each part of each output accumulated EXACTLY and truncated to Py limbs.
+ */
+int orc_cmatvec(int trans, int Pa, int Px, int Pc, int Py, int rows, int cols, const double *A, int lda, long psa,
+                const double *x, long xs, const double *c, long cs, double *y, long ys, int nthreads)
+{
+    if (!valid_p(Pa) || !valid_p(Px) || !valid_p(Py) || (c && !valid_p(Pc)) || lda < rows)
+        return -1;
+    set_threads(nthreads);
+    int nout = trans ? cols : rows;
+    int nin = trans ? rows : cols;
+    const double sa = trans ? -1.0 : 1.0; /* sign of Im(A) in op(A) */
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int o = 0; o < nout; o++) {
+        double ar[ORC_MAXP], ai[ORC_MAXP], xr[ORC_MAXP], xi[ORC_MAXP], out[ORC_MAXP];
+        xacc *re = (xacc *)malloc(sizeof(xacc));
+        xacc *im = (xacc *)malloc(sizeof(xacc));
+        xacc_init(re);
+        xacc_init(im);
+        double sign = 1.0;
+        if (c) {
+            double cv[ORC_MAXP];
+            ldm(Pc, c, cs, o, cv);
+            xacc_add_md(re, Pc, cv, 1.0);
+            ldm(Pc, c + (long)Pc * cs, cs, o, cv);
+            xacc_add_md(im, Pc, cv, 1.0);
+            sign = -1.0;
+        }
+        for (int k = 0; k < nin; k++) {
+            long off = trans ? AT(k, o, lda) : AT(o, k, lda);
+            ldm(Pa, A, psa, off, ar);
+            ldm(Pa, A + (long)Pa * psa, psa, off, ai);
+            ldm(Px, x, xs, k, xr);
+            ldm(Px, x + (long)Px * xs, xs, k, xi);
+            xacc_add_prod(re, Pa, ar, Px, xr, sign);
+            xacc_add_prod(re, Pa, ai, Px, xi, -sa * sign);
+            xacc_add_prod(im, Pa, ar, Px, xi, sign);
+            xacc_add_prod(im, Pa, ai, Px, xr, sa * sign);
+        }
+        xacc_round(re, Py, out);
+        stm(Py, y, ys, o, out);
+        xacc_round(im, Py, out);
+        stm(Py, y + (long)Py * ys, ys, o, out);
+        free(re);
+        free(im);
     }
     return 0;
 }
