@@ -126,6 +126,53 @@ int mdls_solve(int p, int m, int n, int tile, double *A, int lda, double *b, dou
 const char *mdls_status_string(int status);
 
 /*
+ * Complex least squares (the paper's complex workload: Section 3 replaces the transpose of
+ * Algorithm 2 by the Hermitian transpose; Section 4, Table 5 times the complex double
+ * double QR).  A complex matrix is 2P planes: the P limb planes of the real parts, then the
+ * P limb planes of the imaginary parts (real and imaginary parts kept in separate arrays,
+ * end of Section 2), each ld x cols column-major, plane stride ld * cols.  A complex vector
+ * of length L is 2P planes of L doubles.  n must be a multiple of tile (1..256).  Ownership,
+ * streams, errors and *d_info as for the real calls (d_info: R(k,k) with both parts exactly
+ * zero); these calls use only the caller's stream.
+ *
+ * Householder vectors: for column x with x1 = |x1| e^{i theta} (theta = 0 when x1 = 0) and
+ * sigma = sum_{i>1} |x_i|^2: sigma = 0 gives beta = 0 and R(j,j) = x1; otherwise mu =
+ * sqrt(|x1|^2 + sigma), nu = -sigma/(|x1| + mu) (nu = -mu when x1 = 0), v1 = e^{i theta} nu,
+ * beta = 2 nu^2/(sigma + nu^2) (real), v = x/v1 stored below the diagonal, and R(j,j) =
+ * e^{i theta} mu -- Golub-Van Loan 5.1.1 on |x1|, rotated by the phase of x1, so that
+ * H = I - beta v v^H is Hermitian and H x = R(j,j) e_1.
+ */
+size_t mdls_cworkspace_bytes(int p, int m, int n, int tile);
+
+/*
+ * Complex blocked Householder QR.  A (2P planes of lda x n) is overwritten with R (upper
+ * triangle) and the v_j (below the diagonal, unit first entries not stored); beta stays in
+ * the workspace.  T (may be NULL; 2P planes of ldt x n, ldt >= tile) receives for each tile
+ * block k the upper-triangular T_k with H_{k*tile} ... H_{k*tile+tile-1} = I - Y_k T_k Y_k^H
+ * (diag(T_k) = beta); the paper's W is W_k = -Y_k T_k.  Status -1..-10 for arguments 1..10.
+ */
+int mdls_cqr(int p, int m, int n, int tile, double *A, int lda, double *T, int ldt, void *ws,
+             size_t ws_bytes, hipStream_t stream);
+
+/*
+ * B := Q^H B for the complex m x nrhs B (2P planes of ldb x nrhs), with A and T from mdls_cqr
+ * (same tile): the tile blocks in order, B := (I - Y_k T_k^H Y_k^H) B.
+ */
+int mdls_capply_qh(int p, int m, int n, int tile, const double *A, int lda, const double *T,
+                   int ldt, double *B, int ldb, int nrhs, void *ws, size_t ws_bytes,
+                   hipStream_t stream);
+
+/* Complex tiled back substitution (Algorithm 1): x (2P planes of n) holds y on entry and the
+ * solution of R x = y on exit, R the upper triangle of the leading n x n block (ldr >= n). */
+int mdls_cbacksub(int p, int n, int tile, const double *R, int ldr, double *x, void *ws,
+                  size_t ws_bytes, int *d_info, hipStream_t stream);
+
+/* Complex least squares: A and b (2P planes of m) are overwritten by the factors and Q^H b;
+ * x (2P planes of n) receives the solution of R x = (Q^H b)(0:n). */
+int mdls_csolve(int p, int m, int n, int tile, double *A, int lda, double *b, double *x,
+                void *ws, size_t ws_bytes, int *d_info, hipStream_t stream);
+
+/*
  * Batched least squares: many independent problems of uneven sizes solved in one
  * persistent launch (the paper's least-squares solve, Sections 2-3, per problem; its
  * uneven-size workloads, Section 4).  p is 2 (dd) or 4 (qd); every problem has

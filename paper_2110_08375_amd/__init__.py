@@ -18,6 +18,12 @@ from .mdls import (  # noqa: F401
     batch_plan,
     batch_variants,
     batch_workspace,
+    capply_qh,
+    cbacksub,
+    cqr,
+    csolve,
+    cworkspace,
+    cworkspace_bytes,
     form_q,
     form_w,
     lib,

@@ -6,7 +6,7 @@
 #include <string>
 #include <vector>
 
-#include "mdls_impl.hpp"
+#include "mdls_cplx.hpp"
 
 namespace mdls_impl {
 MDLS_FOR_PRECISION(extern, 1)
@@ -17,6 +17,10 @@ MDLS_BATCH_FOR_PRECISION(extern, 2)
 MDLS_BATCH_FOR_PRECISION(extern, 4)
 MDLS_REFINE_FOR_PRECISION(extern, 4)
 MDLS_REFINE_FOR_PRECISION(extern, 8)
+MDLS_CPLX_FOR_PRECISION(extern, 1)
+MDLS_CPLX_FOR_PRECISION(extern, 2)
+MDLS_CPLX_FOR_PRECISION(extern, 4)
+MDLS_CPLX_FOR_PRECISION(extern, 8)
 }  // namespace mdls_impl
 
 using namespace mdls_impl;
@@ -140,6 +144,26 @@ template <int P>
 struct SolveF {
     template <typename... A>
     static int run(A... a) { return solve_t<P>(a...); }
+};
+template <int P>
+struct CQrF {
+    template <typename... A>
+    static int run(A... a) { return cqr_t<P>(a...); }
+};
+template <int P>
+struct CApplyF {
+    template <typename... A>
+    static int run(A... a) { return capply_qh_t<P>(a...); }
+};
+template <int P>
+struct CBacksubF {
+    template <typename... A>
+    static int run(A... a) { return cbacksub_t<P>(a...); }
+};
+template <int P>
+struct CSolveF {
+    template <typename... A>
+    static int run(A... a) { return csolve_t<P>(a...); }
 };
 template <int P>
 struct QrF {
@@ -294,6 +318,79 @@ int mdls_backsub(int p, int n, int tile, const double *R, int ldr, double *x, vo
     if (ws_bytes < mdls_workspace_bytes(p, n, n, tile)) return -8;
     if (!d_info) return -9;
     return dispatch<BacksubF>(p, n, tile, R, ldr, x, ws, d_info, stream);
+}
+
+size_t mdls_cworkspace_bytes(int p, int m, int n, int tile)
+{
+    if (!valid_p(p) || n < 1 || m < n || !valid_tile(tile)) return 0;
+    return clayout(p, m, n, tile).total;
+}
+
+int mdls_cqr(int p, int m, int n, int tile, double *A, int lda, double *T, int ldt, void *ws, size_t ws_bytes,
+             hipStream_t stream)
+{
+    if (!valid_p(p)) return -1;
+    if (m < 1) return -2;
+    if (n < 1 || n > m) return -3;
+    if (!valid_tile(tile) || n % tile != 0) return -4;
+    if (!A) return -5;
+    if (lda < m) return -6;
+    if (T && ldt < tile) return -8;
+    if (!ws) return -9;
+    if (ws_bytes < mdls_cworkspace_bytes(p, m, n, tile)) return -10;
+    return dispatch<CQrF>(p, m, n, tile, A, lda, T, ldt, ws, stream);
+}
+
+int mdls_capply_qh(int p, int m, int n, int tile, const double *A, int lda, const double *T, int ldt, double *B,
+                   int ldb, int nrhs, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    if (!valid_p(p)) return -1;
+    if (m < 1) return -2;
+    if (n < 1 || n > m) return -3;
+    if (!valid_tile(tile) || n % tile != 0) return -4;
+    if (!A) return -5;
+    if (lda < m) return -6;
+    if (!T) return -7;
+    if (ldt < tile) return -8;
+    if (!B && nrhs > 0) return -9;
+    if (ldb < m) return -10;
+    if (nrhs < 0) return -11;
+    if (!ws) return -12;
+    if (ws_bytes < mdls_cworkspace_bytes(p, m, n, tile)) return -13;
+    if (nrhs == 0) return 0;
+    return dispatch<CApplyF>(p, m, n, tile, A, lda, T, ldt, B, ldb, nrhs, ws, stream);
+}
+
+int mdls_cbacksub(int p, int n, int tile, const double *R, int ldr, double *x, void *ws, size_t ws_bytes, int *d_info,
+                  hipStream_t stream)
+{
+    if (!valid_p(p)) return -1;
+    if (n < 1) return -2;
+    if (!valid_tile(tile) || n % tile != 0) return -3;
+    if (!R) return -4;
+    if (ldr < n) return -5;
+    if (!x) return -6;
+    if (!ws) return -7;
+    if (ws_bytes < mdls_cworkspace_bytes(p, n, n, tile)) return -8;
+    if (!d_info) return -9;
+    return dispatch<CBacksubF>(p, n, tile, R, ldr, x, ws, d_info, stream);
+}
+
+int mdls_csolve(int p, int m, int n, int tile, double *A, int lda, double *b, double *x, void *ws, size_t ws_bytes,
+                int *d_info, hipStream_t stream)
+{
+    if (!valid_p(p)) return -1;
+    if (m < 1) return -2;
+    if (n < 1 || n > m) return -3;
+    if (!valid_tile(tile) || n % tile != 0) return -4;
+    if (!A) return -5;
+    if (lda < m) return -6;
+    if (!b) return -7;
+    if (!x) return -8;
+    if (!ws) return -9;
+    if (ws_bytes < mdls_cworkspace_bytes(p, m, n, tile)) return -10;
+    if (!d_info) return -11;
+    return dispatch<CSolveF>(p, m, n, tile, A, lda, b, x, ws, d_info, stream);
 }
 
 int mdls_solve(int p, int m, int n, int tile, double *A, int lda, double *b, double *x, void *ws, size_t ws_bytes,

@@ -1,0 +1,703 @@
+// mdls_cplx.hpp -- complex multiple-double least squares on gfx950: Householder QR with the
+// Hermitian transpose in place of the transpose (paper Section 3, text after the W
+// recurrence), Q^H b and the tiled back substitution (Section 2, Algorithm 1) on complex
+// numbers; the paper's complex workload is the double double QR of Section 4, Table 5.
+//
+// Storage: a complex matrix is 2P planes, the P limb planes of the real parts followed by
+// the P limb planes of the imaginary parts (the paper keeps real and imaginary parts in
+// separate arrays, end of Section 2); every plane has the same stride ps and is column-major
+// with leading dimension ld.  A complex vector of length L is 2P planes of L doubles.
+//
+// Householder vector of a column x (x1 = |x1| e^{i theta}, theta = 0 when x1 = 0): with
+// sigma = sum_{i>1} |x_i|^2 and mu = sqrt(|x1|^2 + sigma), the Golub-Van Loan 5.1.1 choice is
+// made on the modulus and rotated by the phase: nu = -sigma/(|x1| + mu) (nu = -mu when
+// x1 = 0), v1 = e^{i theta} nu, beta = 2 nu^2/(sigma + nu^2), v = x/v1, and R_jj =
+// e^{i theta} mu; sigma = 0 gives beta = 0 and R_jj = x1.  H = I - beta v v^H is Hermitian.
+//
+// Kernels (one QR panel of b = tile columns at a time):
+//   k_crefl   -- the reflector of the panel's first column (one workgroup);
+//   k_cstep   -- for panel column j: H_j applied to the panel columns right of j, one
+//                workgroup per column; workgroup 0 then forms the reflector of column j+1
+//                from the column it has just updated, so one launch per column carries the
+//                panel's serial chain;
+//   k_cgram   -- G = Y^H Y (strictly upper part) of the panel;
+//   k_cinvert -- T = (diag(1/beta) + triu(G, 1))^{-1} column-parallel, with the diagonal of
+//                the inverse supplied as beta (so beta_j = 0 gives a zero row and column, the
+//                identity reflector); also the diagonal tiles of R for the back substitution;
+//   k_ctn, k_ctrmm_h, k_cnn_sub -- the trailing update C := (I - Y T^H Y^H) C, which is the
+//                paper's C + Y W^H C with W = -Y T, and the same for Q^H B;
+//   k_cbs_xi, k_cbs_upd -- x_i := U_i^{-1} b_i and b_j -= A_{j,i} x_i.
+#pragma once
+#include "mdls_impl.hpp"
+
+namespace mdls_impl {
+
+// ============================================================================ complex md values
+template <int P>
+struct CV {
+    V<P> re, im;
+};
+
+template <int P>
+struct CAcc {
+    Acc<P> re, im;
+};
+
+// each complex multiply-add puts two terms into each part's accumulator
+template <int P>
+constexpr int kCLazy = (kLazy<P> / 2 > 0) ? kLazy<P> / 2 : 1;
+
+template <int P>
+__device__ __forceinline__ CV<P> czero()
+{
+    return CV<P>{zero<P>(), zero<P>()};
+}
+
+template <int P>
+__device__ __forceinline__ CV<P> cone()
+{
+    return CV<P>{from_double<P>(1.0), zero<P>()};
+}
+
+template <int P>
+__device__ __forceinline__ CV<P> cneg(const CV<P> &a)
+{
+    return CV<P>{neg(a.re), neg(a.im)};
+}
+
+template <int P>
+__device__ __forceinline__ CV<P> cldm(const double *X, long ps, long off)
+{
+    return CV<P>{ldm<P>(X, ps, off), ldm<P>(X + (long)P * ps, ps, off)};
+}
+
+template <int P>
+__device__ __forceinline__ void cstm(double *X, long ps, long off, const CV<P> &v)
+{
+    stm(X, ps, off, v.re);
+    stm(X + (long)P * ps, ps, off, v.im);
+}
+
+template <int P>
+__device__ __forceinline__ CV<P> clds_ld(const double *s)
+{
+    return CV<P>{lds_ld<P>(s), lds_ld<P>(s + P)};
+}
+
+template <int P>
+__device__ __forceinline__ void clds_st(double *s, const CV<P> &v)
+{
+    lds_st(s, v.re);
+    lds_st(s + P, v.im);
+}
+
+template <int P>
+__device__ __forceinline__ CAcc<P> cacc_zero()
+{
+    return CAcc<P>{acc_zero<P>(), acc_zero<P>()};
+}
+
+template <int P>
+__device__ __forceinline__ CAcc<P> cacc_from(const CV<P> &c)
+{
+    return CAcc<P>{acc_from(c.re), acc_from(c.im)};
+}
+
+template <int P>
+__device__ __forceinline__ CV<P> cacc_get(const CAcc<P> &a)
+{
+    return CV<P>{acc_get(a.re), acc_get(a.im)};
+}
+
+// acc += op(a) b with op(a) = conj(a) when CONJ, else a
+template <int P, bool CONJ>
+__device__ __forceinline__ void cacc_fma(CAcc<P> &acc, const CV<P> &a, const CV<P> &b)
+{
+    const V<P> nai = neg(a.im);
+    acc_fma(acc.re, a.re, b.re);
+    acc_fma(acc.re, CONJ ? a.im : nai, b.im);
+    acc_fma(acc.im, a.re, b.im);
+    acc_fma(acc.im, CONJ ? nai : a.im, b.re);
+}
+
+// the same as term number i of a long accumulation
+template <int P, bool CONJ>
+__device__ __forceinline__ void cacc_fma_step(CAcc<P> &acc, const CV<P> &a, const CV<P> &b, int i)
+{
+    cacc_fma<P, CONJ>(acc, a, b);
+    if (((i + 1) % kCLazy<P>) == 0) {
+        acc.re = acc_from(acc_get(acc.re));
+        acc.im = acc_from(acc_get(acc.im));
+    }
+}
+
+template <int P>
+__device__ __forceinline__ CV<P> cmul(const CV<P> &a, const CV<P> &b)
+{
+    CAcc<P> t = cacc_zero<P>();
+    cacc_fma<P, false>(t, a, b);
+    return cacc_get(t);
+}
+
+// c - a b
+template <int P>
+__device__ __forceinline__ CV<P> cfms(const CV<P> &c, const CV<P> &a, const CV<P> &b)
+{
+    CAcc<P> t = cacc_from(c);
+    cacc_fma<P, false>(t, cneg(a), b);
+    return cacc_get(t);
+}
+
+template <int P>
+__device__ __forceinline__ CV<P> cadd(const CV<P> &a, const CV<P> &b)
+{
+    return CV<P>{add(a.re, b.re), add(a.im, b.im)};
+}
+
+// a s for a real s
+template <int P>
+__device__ __forceinline__ CV<P> cscale(const CV<P> &a, const V<P> &s)
+{
+    return CV<P>{mul(a.re, s), mul(a.im, s)};
+}
+
+template <int P>
+__device__ __forceinline__ V<P> cabs2(const CV<P> &a)
+{
+    Acc<P> t = acc_zero<P>();
+    acc_fma(t, a.re, a.re);
+    acc_fma(t, a.im, a.im);
+    return acc_get(t);
+}
+
+// 1/b = conj(b) / |b|^2
+template <int P>
+__device__ __forceinline__ CV<P> crecip(const CV<P> &b)
+{
+    const V<P> d = recip(cabs2(b));
+    return CV<P>{mul(b.re, d), neg(mul(b.im, d))};
+}
+
+template <int P>
+__device__ __forceinline__ CV<P> cwave_sum(const CV<P> &v)
+{
+    return CV<P>{wave_sum(v.re), wave_sum(v.im)};
+}
+
+// Sum over the workgroup, the same bits in every thread (waves combined in a fixed order).
+// sred holds (kThreads / 64) * 2P doubles; called by all threads.
+template <int P>
+__device__ __forceinline__ CV<P> cblock_sum(const CV<P> &v, double *sred)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const CV<P> w = cwave_sum(v);
+    if (lane == 0) clds_st(&sred[wid * 2 * P], w);
+    __syncthreads();
+    CV<P> s = clds_ld<P>(&sred[0]);
+    for (int k = 1; k < kThreads / 64; ++k) s = cadd(s, clds_ld<P>(&sred[k * 2 * P]));
+    __syncthreads();
+    return s;
+}
+
+template <int P>
+__device__ __forceinline__ V<P> rblock_sum(const V<P> &v, double *sred)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const V<P> w = wave_sum(v);
+    if (lane == 0) lds_st(&sred[wid * P], w);
+    __syncthreads();
+    V<P> s = lds_ld<P>(&sred[0]);
+    for (int k = 1; k < kThreads / 64; ++k) s = add(s, lds_ld<P>(&sred[k * P]));
+    __syncthreads();
+    return s;
+}
+
+// Entry (r, c) of the unit lower trapezoidal block Y (h rows, w columns) stored below the
+// diagonal of A: 1 on the diagonal, 0 above it.
+template <int P>
+__device__ __forceinline__ CV<P> cy_entry(const double *Y, long ldy, long psy, long r, int c, int h, int w)
+{
+    if (r >= h || c >= w || r < c) return czero<P>();
+    if (r == c) return cone<P>();
+    return cldm<P>(Y, psy, (long)c * ldy + r);
+}
+
+// ============================================================================ QR panel
+struct CPanelArgs {
+    double *A;  // whole matrix, 2P planes of stride ps, leading dimension lda
+    long lda, ps;
+    int m;
+    int j;     // k_cstep: the column whose reflector is applied; k_crefl: the column to reduce
+    int jend;  // one past the panel's last column
+    double *beta;  // P planes of stride bps
+    long bps;
+};
+
+// The reflector of column c (rows c..m-1), formed by one whole workgroup: beta_c, v below the
+// diagonal, R_cc on it.
+template <int P>
+__device__ void c_reflector(double *A, long lda, long ps, int m, int c, double *beta, long bps, double *sred)
+{
+    const int tid = threadIdx.x;
+    const long off = (long)c * lda;
+    // every thread reads x1 before the barriers of the reduction; thread 0 overwrites it last
+    const CV<P> alpha = cldm<P>(A, ps, off + c);
+    Acc<P> acc = acc_zero<P>();
+    int nt = 0;
+    for (long r = c + 1 + tid; r < m; r += kThreads) {
+        const CV<P> x = cldm<P>(A, ps, off + r);
+        acc_fma(acc, x.re, x.re);
+        acc_fma(acc, x.im, x.im);
+        if (((++nt) % kCLazy<P>) == 0) acc = acc_from(acc_get(acc));
+    }
+    const V<P> sig = rblock_sum(acc_get(acc), sred);
+    if (is_zero(sig)) {  // identity reflector, R_cc = x1
+        if (tid == 0) stm(beta, bps, c, zero<P>());
+        return;
+    }
+    const V<P> a2 = cabs2(alpha);
+    const V<P> mu = sqrt_md(add(a2, sig));
+    const V<P> rho = sqrt_md(a2);
+    CV<P> ph;
+    V<P> nu;
+    if (is_zero(rho)) {
+        ph = cone<P>();
+        nu = neg(mu);
+    } else {
+        const V<P> ir = recip(rho);
+        ph = CV<P>{mul(alpha.re, ir), mul(alpha.im, ir)};
+        nu = neg(div(sig, add(rho, mu)));
+    }
+    const V<P> nu2 = mul(nu, nu);
+    const V<P> bt = div(scale(nu2, 2.0), add(sig, nu2));
+    const CV<P> iv = crecip(cscale(ph, nu));  // 1 / v1
+    for (long r = c + 1 + tid; r < m; r += kThreads) cstm(A, ps, off + r, cmul(cldm<P>(A, ps, off + r), iv));
+    if (tid == 0) {
+        stm(beta, bps, c, bt);
+        cstm(A, ps, off + c, cscale(ph, mu));
+    }
+}
+
+template <int P>
+__global__ __launch_bounds__(kThreads) void k_crefl(CPanelArgs g)
+{
+    __shared__ double sred[(kThreads / 64) * 2 * P];
+    c_reflector<P>(g.A, g.lda, g.ps, g.m, g.j, g.beta, g.bps, sred);
+}
+
+// Workgroup b: column c = j + 1 + b of the panel := H_j column (rows j..m-1, v_j = 1
+// implicit); workgroup 0 then forms the reflector of column j + 1.  Each row is read and
+// written by the same thread, so the only cross-thread hand-off is the barrier before
+// c_reflector.
+template <int P>
+__global__ __launch_bounds__(kThreads) void k_cstep(CPanelArgs g)
+{
+    __shared__ double sred[(kThreads / 64) * 2 * P];
+    const int c = g.j + 1 + blockIdx.x;
+    const int tid = threadIdx.x;
+    const long offj = (long)g.j * g.lda, offc = (long)c * g.lda;
+    const V<P> bt = ldm<P>(g.beta, g.bps, g.j);
+    if (!is_zero(bt)) {
+        CAcc<P> acc = cacc_zero<P>();
+        int nt = 0;
+        for (long r = g.j + tid; r < g.m; r += kThreads) {
+            const CV<P> v = (r == g.j) ? cone<P>() : cldm<P>(g.A, g.ps, offj + r);
+            cacc_fma_step<P, true>(acc, v, cldm<P>(g.A, g.ps, offc + r), nt++);
+        }
+        const CV<P> w = cblock_sum(cacc_get(acc), sred);  // v^H a_c
+        const CV<P> nt_ = cneg(cscale(w, bt));              // -beta v^H a_c
+        for (long r = g.j + tid; r < g.m; r += kThreads) {
+            const CV<P> v = (r == g.j) ? cone<P>() : cldm<P>(g.A, g.ps, offj + r);
+            CAcc<P> a = cacc_from(cldm<P>(g.A, g.ps, offc + r));
+            cacc_fma<P, false>(a, v, nt_);
+            cstm(g.A, g.ps, offc + r, cacc_get(a));
+        }
+    }
+    if (blockIdx.x == 0) {
+        __syncthreads();
+        c_reflector<P>(g.A, g.lda, g.ps, g.m, c, g.beta, g.bps, sred);
+    }
+}
+
+// G(l, j) = y_l^H y_j for l < j (zero for l >= j) of the block Y (h rows, tile columns);
+// workgroup j, one wave per l.
+template <int P>
+__global__ __launch_bounds__(kThreads) void k_cgram(const double *Y, long lda, long ps, int h, int tile, double *G,
+                                                   long gps)
+{
+    const int j = blockIdx.x;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int l = wid; l < tile; l += kThreads / 64) {
+        if (l >= j) {
+            if (lane == 0) cstm(G, gps, (long)j * tile + l, czero<P>());
+            continue;
+        }
+        CAcc<P> acc = cacc_zero<P>();
+        int nt = 0;
+        for (int r = j + lane; r < h; r += 64)  // y_j is zero above row j
+            cacc_fma_step<P, true>(acc, cy_entry<P>(Y, lda, ps, r, l, h, tile), cy_entry<P>(Y, lda, ps, r, j, h, tile),
+                                   nt++);
+        const CV<P> s = cwave_sum(cacc_get(acc));
+        if (lane == 0) cstm(G, gps, (long)j * tile + l, s);
+    }
+}
+
+// ============================================================================ triangular inverse
+// X = U^{-1} for complex upper-triangular tiles, NC columns per workgroup, all advancing one
+// row at a time from the bottom (paper Algorithm 1, stage 1): x_i = r_i d_i, then
+// r_k -= U(k, i) x_i for k < i.  d_i = 1/U(i, i), or the real dsup_i when supplied (the T
+// factor, whose inverse diagonal is beta).  Same InvArgs as the real kernel; the imaginary
+// planes follow the real ones at P plane strides.
+template <int P, int NC, int RPT>
+__global__ __launch_bounds__(kThreads) void k_cinvert(InvArgs g)
+{
+    constexpr int RG = kThreads / NC;
+    constexpr int Q = 2 * P;
+    __shared__ double sD[256 * Q];
+    __shared__ double sX[2][NC * Q];
+    __shared__ double sU[2][256 * Q];
+    const int t = blockIdx.y;
+    const int c0 = blockIdx.x * NC;
+    const int tid = threadIdx.x;
+    const int jl = tid % NC, rg = tid / NC;
+    const int j = c0 + jl;
+    const double *U = g.U + (long)t * g.ustride;
+    double *X = g.X + (long)t * g.xstride;
+    const int c1 = min(c0 + NC, g.tile);
+
+    for (int i = tid; i < c1; i += kThreads) {
+        CV<P> d;
+        if (g.dsup)
+            d = CV<P>{ldm<P>(g.dsup + (long)t * g.tile, g.dps, i), zero<P>()};
+        else
+            d = crecip(cldm<P>(U, g.psu, (long)i * g.ldu + i));
+        clds_st(&sD[i * Q], d);
+    }
+    CV<P> r[RPT];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int k = rg + q * RG;
+        r[q] = (k == j) ? cone<P>() : czero<P>();
+        if (j < g.tile && k < g.tile && k > j) cstm(X, g.psx, (long)j * g.ldx + k, czero<P>());
+    }
+    if (c1 > 0 && tid < c1 - 1) clds_st(&sU[(c1 - 1) & 1][tid * Q], cldm<P>(U, g.psu, (long)(c1 - 1) * g.ldu + tid));
+    __syncthreads();
+    for (int i = c1 - 1; i >= 0; --i) {
+        const int buf = i & 1;
+        CV<P> unext = czero<P>();
+        const bool pre = i > 0 && tid < i - 1;
+        if (pre) unext = cldm<P>(U, g.psu, (long)(i - 1) * g.ldu + tid);
+        if (j < c1 && j >= i && (i % RG) == rg) {
+            const int qi = i / RG;
+            CV<P> xv = czero<P>();
+#pragma unroll
+            for (int q = 0; q < RPT; ++q)
+                if (q == qi) xv = cmul(r[q], clds_ld<P>(&sD[i * Q]));
+            clds_st(&sX[buf][jl * Q], xv);
+            cstm(X, g.psx, (long)j * g.ldx + i, xv);
+        }
+        __syncthreads();
+        if (j < c1 && j >= i) {
+            const CV<P> xv = clds_ld<P>(&sX[buf][jl * Q]);
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) {
+                const int k = rg + q * RG;
+                if (k < i) r[q] = cfms(r[q], clds_ld<P>(&sU[buf][k * Q]), xv);
+            }
+        }
+        // sU[buf ^ 1] was last read in step i + 1, before this step's barrier
+        if (pre) clds_st(&sU[buf ^ 1][tid * Q], unext);
+    }
+}
+
+// ============================================================================ block reflector
+// S(l, c) = y_l^H B(:, c): one wave per (l, c)
+template <int P>
+__global__ __launch_bounds__(kThreads) void k_ctn(const double *Y, long lda, long ps, int h, int tile, const double *B,
+                                                 long ldb, long bps, int nrhs, double *S, long sps)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int l = blockIdx.x * (kThreads / 64) + wid, c = blockIdx.y;
+    if (l >= tile || c >= nrhs) return;
+    CAcc<P> acc = cacc_zero<P>();
+    int nt = 0;
+    for (int r = l + lane; r < h; r += 64)
+        cacc_fma_step<P, true>(acc, cy_entry<P>(Y, lda, ps, r, l, h, tile), cldm<P>(B, bps, (long)c * ldb + r), nt++);
+    const CV<P> s = cwave_sum(cacc_get(acc));
+    if (lane == 0) cstm(S, sps, (long)c * tile + l, s);
+}
+
+// U(i, c) = sum_{l <= i} conj(T(l, i)) S(l, c), i.e. U = T^H S
+template <int P>
+__global__ __launch_bounds__(kThreads) void k_ctrmm_h(const double *T, long ldt, long tps, const double *S, long sps,
+                                                     double *U, int tile, int nrhs)
+{
+    const int i = blockIdx.x * kThreads + threadIdx.x, c = blockIdx.y;
+    if (i >= tile || c >= nrhs) return;
+    CAcc<P> acc = cacc_zero<P>();
+    for (int l = 0; l <= i; ++l)
+        cacc_fma_step<P, true>(acc, cldm<P>(T, tps, (long)i * ldt + l), cldm<P>(S, sps, (long)c * tile + l), l);
+    cstm(U, sps, (long)c * tile + i, cacc_get(acc));
+}
+
+// B(r, c) -= sum_l Y(r, l) U(l, c), r < h
+template <int P>
+__global__ __launch_bounds__(kThreads) void k_cnn_sub(const double *Y, long lda, long ps, int h, int tile, const double *U,
+                                                     long ups, double *B, long ldb, long bps)
+{
+    const long r = (long)blockIdx.x * kThreads + threadIdx.x;
+    const int c = blockIdx.y;
+    if (r >= h) return;
+    CAcc<P> acc = cacc_from(cldm<P>(B, bps, (long)c * ldb + r));
+    const int lmax = (r < tile - 1) ? (int)r : tile - 1;
+    for (int l = 0; l <= lmax; ++l)
+        cacc_fma_step<P, false>(acc, cneg(cy_entry<P>(Y, lda, ps, r, l, h, tile)), cldm<P>(U, ups, (long)c * tile + l), l);
+    cstm(B, bps, (long)c * ldb + r, cacc_get(acc));
+}
+
+// ============================================================================ back substitution
+// x_i := Xinv_i y_i, one wave per output row
+template <int P>
+__global__ __launch_bounds__(kThreads) void k_cbs_xi(const double *Xi, long ldx, long psx, const double *y, long yps,
+                                                    double *x, long xps, int tile)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int row = blockIdx.x * (kThreads / 64) + wid;
+    if (row >= tile) return;
+    CAcc<P> acc = cacc_zero<P>();
+    int nt = 0;
+    for (int c = row + lane; c < tile; c += 64)
+        cacc_fma_step<P, false>(acc, cldm<P>(Xi, psx, (long)c * ldx + row), cldm<P>(y, yps, c), nt++);
+    const CV<P> s = cwave_sum(cacc_get(acc));
+    if (lane == 0) cstm(x, xps, row, s);
+}
+
+// y(0:rows) -= R(0:rows, columns of tile i) x_i; 64 rows per workgroup, the tile's columns
+// split over the waves and combined in a fixed order
+template <int P>
+__global__ __launch_bounds__(kThreads) void k_cbs_upd(const double *Rc, long ldr, long psr, const double *xi, long xps,
+                                                     double *y, long yps, int rows, int tile)
+{
+    constexpr int Q = 2 * P, NW = kThreads / 64;
+    __shared__ double sx[256 * Q];
+    __shared__ double sp[NW][64 * Q];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int c = threadIdx.x; c < tile; c += kThreads) clds_st(&sx[c * Q], cldm<P>(xi, xps, c));
+    __syncthreads();
+    const long row = (long)blockIdx.x * 64 + lane;
+    const int q = (tile + NW - 1) / NW;
+    const int cb = wid * q, ce = min(tile, cb + q);
+    CAcc<P> acc = cacc_zero<P>();
+    if (row < rows)
+        for (int c = cb; c < ce; ++c)
+            cacc_fma_step<P, false>(acc, cldm<P>(Rc, psr, (long)c * ldr + row), clds_ld<P>(&sx[c * Q]), c - cb);
+    clds_st(&sp[wid][lane * Q], cacc_get(acc));
+    __syncthreads();
+    if (wid == 0 && row < rows) {
+        CV<P> s = clds_ld<P>(&sp[0][lane * Q]);
+        for (int w = 1; w < NW; ++w) s = cadd(s, clds_ld<P>(&sp[w][lane * Q]));
+        cstm(y, yps, row, cadd(cldm<P>(y, yps, row), cneg(s)));
+    }
+}
+
+// ============================================================================ host side
+// columns per workgroup of k_cinvert: keeps the RPT complex row values of a thread in
+// registers (RPT = tile rows / row groups)
+template <int P>
+constexpr int kCInvCols = (P <= 2) ? 16 : (P == 4 ? 8 : 4);
+
+struct CLayout {
+    size_t beta, T, G, S, U, y, total;
+    int sc;  // columns of S and U
+};
+
+inline CLayout clayout(int P, int m, int n, int tile)
+{
+    CLayout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off += align256(bytes);
+        return at;
+    };
+    L.sc = n > 64 ? n : 64;
+    const size_t blk = sizeof(double) * 2 * (size_t)P * tile * n;  // 2P planes of tile x n
+    L.beta = take(sizeof(double) * (size_t)P * n);
+    L.T = take(blk);
+    L.G = take(blk);
+    L.S = take(sizeof(double) * 2 * (size_t)P * tile * L.sc);
+    L.U = take(sizeof(double) * 2 * (size_t)P * tile * L.sc);
+    L.y = take(sizeof(double) * 2 * (size_t)P * (m > n ? m : n));
+    L.total = off;
+    return L;
+}
+
+template <int P>
+void cinvert_tiles(const InvArgs &ia, int ntiles, hipStream_t s)
+{
+    constexpr int NC = kCInvCols<P>;
+    constexpr int RPT = 256 / (kThreads / NC);
+    dim3 grid((ia.tile + NC - 1) / NC, ntiles);
+    MDLS_LAUNCH("k_cinvert", P, 4.0 * ntiles * ia.tile * ia.tile * ia.tile / 6.0, (k_cinvert<P, NC, RPT>), grid,
+                dim3(kThreads), s, ia);
+}
+
+// B(kt:m, cols) := (I - Y_k op(T_k) Y_k^H) B(kt:m, cols) for nc columns: S = Y^H B, U = op(T) S,
+// B -= Y U, with op(T) = T^H (the product Q^H and the QR's trailing update)
+template <int P>
+void cblock_apply_h(const double *Y, long lda, long psa, int h, int tile, const double *Tk, long ldt, long tps, double *B,
+                    long ldb, long bps, int nc, double *S, double *U, long sps, hipStream_t s)
+{
+    MDLS_LAUNCH("k_ctn", P, 4.0 * h * tile * nc, (k_ctn<P>), dim3((tile + 3) / 4, nc), dim3(kThreads), s, Y, lda, psa, h,
+                tile, B, ldb, bps, nc, S, sps);
+    MDLS_LAUNCH("k_ctrmm_h", P, 2.0 * tile * tile * nc, (k_ctrmm_h<P>), dim3((tile + kThreads - 1) / kThreads, nc),
+                dim3(kThreads), s, Tk, ldt, tps, S, sps, U, tile, nc);
+    MDLS_LAUNCH("k_cnn_sub", P, 4.0 * h * tile * nc, (k_cnn_sub<P>), dim3((h + kThreads - 1) / kThreads, nc),
+                dim3(kThreads), s, Y, lda, psa, h, tile, U, sps, B, ldb, bps);
+}
+
+// Blocked complex Householder QR; T (2P planes of ldt x n) receives T_k for every tile block.
+template <int P>
+int cqr_t(int m, int n, int tile, double *A, int lda, double *T, int ldt, void *ws, hipStream_t s)
+{
+    const CLayout L = clayout(P, m, n, tile);
+    char *w = (char *)ws;
+    double *beta = (double *)(w + L.beta);
+    double *G = (double *)(w + L.G);
+    double *S = (double *)(w + L.S);
+    double *U = (double *)(w + L.U);
+    if (!T) {
+        T = (double *)(w + L.T);
+        ldt = tile;
+    }
+    const long psa = (long)lda * n, tps = (long)ldt * n, gps = (long)tile * tile, sps = (long)tile * L.sc;
+    const int N = n / tile;
+    CPanelArgs pa{A, (long)lda, psa, m, 0, 0, beta, (long)n};
+    for (int k = 0; k < N; ++k) {
+        const int kt = k * tile, jend = kt + tile;
+        const int h = m - kt;
+        pa.j = kt;
+        pa.jend = jend;
+        MDLS_LAUNCH("k_crefl", P, 6.0 * h, (k_crefl<P>), dim3(1), dim3(kThreads), s, pa);
+        for (int j = kt; j < jend - 1; ++j) {
+            pa.j = j;
+            MDLS_LAUNCH("k_cstep", P, 8.0 * (m - j) * (jend - j - 1) + 6.0 * (m - j - 1), (k_cstep<P>),
+                        dim3(jend - j - 1), dim3(kThreads), s, pa);
+        }
+        const double *Y = A + (long)kt * lda + kt;
+        MDLS_LAUNCH("k_cgram", P, 2.0 * h * tile * tile, (k_cgram<P>), dim3(tile), dim3(kThreads), s, Y, (long)lda, psa, h,
+                    tile, G, gps);
+        InvArgs ia;
+        ia.U = G;
+        ia.ldu = tile;
+        ia.psu = gps;
+        ia.ustride = 0;
+        ia.dsup = beta + kt;
+        ia.dps = n;
+        ia.X = T + (long)kt * ldt;
+        ia.ldx = ldt;
+        ia.psx = tps;
+        ia.xstride = 0;
+        ia.tile = tile;
+        cinvert_tiles<P>(ia, 1, s);
+        if (jend < n)
+            cblock_apply_h<P>(Y, (long)lda, psa, h, tile, T + (long)kt * ldt, (long)ldt, tps, A + (long)jend * lda + kt,
+                              (long)lda, psa, n - jend, S, U, sps, s);
+    }
+    return hipGetLastError() == hipSuccess ? 0 : MDLS_EHIP;
+}
+
+// B := Q^H B (m x nrhs, 2P planes of ldb x nrhs)
+template <int P>
+int capply_qh_t(int m, int n, int tile, const double *A, int lda, const double *T, int ldt, double *B, int ldb, int nrhs,
+                void *ws, hipStream_t s)
+{
+    const CLayout L = clayout(P, m, n, tile);
+    char *w = (char *)ws;
+    double *S = (double *)(w + L.S);
+    double *U = (double *)(w + L.U);
+    const long psa = (long)lda * n, tps = (long)ldt * n, bps = (long)ldb * nrhs, sps = (long)tile * L.sc;
+    const int N = n / tile;
+    for (int c0 = 0; c0 < nrhs; c0 += L.sc) {
+        const int nc = (nrhs - c0 < L.sc) ? nrhs - c0 : L.sc;
+        double *Bc = B + (long)c0 * ldb;
+        for (int k = 0; k < N; ++k) {
+            const long kt = (long)k * tile;
+            cblock_apply_h<P>(A + kt * lda + kt, (long)lda, psa, m - (int)kt, tile, T + kt * ldt, (long)ldt, tps, Bc + kt,
+                              (long)ldb, bps, nc, S, U, sps, s);
+        }
+    }
+    return hipGetLastError() == hipSuccess ? 0 : MDLS_EHIP;
+}
+
+// tiled back substitution on y (2P planes of n); x receives the solution
+template <int P>
+void cbacksub_tiles(const CLayout &L, char *w, int n, int tile, const double *R, long ldr, long psr, double *y, double *x,
+                    long xps, int *d_info, hipStream_t s)
+{
+    const int N = n / tile;
+    MDLS_LAUNCH("k_diag_check", P, 0, k_diag_check, dim3(1), dim3(kThreads), s, R, ldr, psr, n, 2 * P, d_info);
+    double *Xinv = (double *)(w + L.G);
+    const long xips = (long)tile * n;
+    InvArgs ia;
+    ia.U = R;
+    ia.ldu = ldr;
+    ia.psu = psr;
+    ia.ustride = (long)tile * (ldr + 1);
+    ia.dsup = nullptr;
+    ia.dps = 0;
+    ia.X = Xinv;
+    ia.ldx = tile;
+    ia.psx = xips;
+    ia.xstride = (long)tile * tile;
+    ia.tile = tile;
+    cinvert_tiles<P>(ia, N, s);
+    const long yps = n;
+    for (int i = N - 1; i >= 0; --i) {
+        const long it = (long)i * tile;
+        MDLS_LAUNCH("k_cbs_xi", P, 2.0 * tile * tile, (k_cbs_xi<P>), dim3((tile + 3) / 4), dim3(kThreads), s,
+                    Xinv + (long)i * tile * tile, (long)tile, xips, y + it, yps, x + it, xps, tile);
+        if (i > 0) {
+            const int rows = i * tile;
+            MDLS_LAUNCH("k_cbs_upd", P, 4.0 * rows * tile, (k_cbs_upd<P>), dim3((rows + 63) / 64), dim3(kThreads), s,
+                        R + it * ldr, ldr, psr, x + it, xps, y, yps, rows, tile);
+        }
+    }
+}
+
+template <int P>
+int cbacksub_t(int n, int tile, const double *R, int ldr, double *x, void *ws, int *d_info, hipStream_t s)
+{
+    const CLayout L = clayout(P, n, n, tile);
+    char *w = (char *)ws;
+    double *y = (double *)(w + L.y);
+    MDLS_LAUNCH("k_copy", P, 0, k_copy, dim3((n + 255) / 256), dim3(256), s, x, (long)n, y, (long)n, n, 2 * P);
+    cbacksub_tiles<P>(L, w, n, tile, R, ldr, (long)ldr * n, y, x, n, d_info, s);
+    return hipGetLastError() == hipSuccess ? 0 : MDLS_EHIP;
+}
+
+// Complex least squares: A and b overwritten by the factors and Q^H b; x gets the solution.
+template <int P>
+int csolve_t(int m, int n, int tile, double *A, int lda, double *b, double *x, void *ws, int *d_info, hipStream_t s)
+{
+    const CLayout L = clayout(P, m, n, tile);
+    char *w = (char *)ws;
+    double *T = (double *)(w + L.T);
+    int rc = cqr_t<P>(m, n, tile, A, lda, T, tile, ws, s);
+    if (rc) return rc;
+    rc = capply_qh_t<P>(m, n, tile, A, lda, T, tile, b, m, 1, ws, s);
+    if (rc) return rc;
+    double *y = (double *)(w + L.y);
+    MDLS_LAUNCH("k_copy", P, 0, k_copy, dim3((n + 255) / 256), dim3(256), s, b, (long)m, y, (long)n, n, 2 * P);
+    cbacksub_tiles<P>(L, w, n, tile, A, lda, (long)lda * n, y, x, n, d_info, s);
+    return hipGetLastError() == hipSuccess ? 0 : MDLS_EHIP;
+}
+
+#define MDLS_CPLX_FOR_PRECISION(X, P)                                                                               \
+    X template int cqr_t<P>(int, int, int, double *, int, double *, int, void *, hipStream_t);                      \
+    X template int capply_qh_t<P>(int, int, int, const double *, int, const double *, int, double *, int, int,      \
+                                  void *, hipStream_t);                                                            \
+    X template int cbacksub_t<P>(int, int, const double *, int, double *, void *, int *, hipStream_t);             \
+    X template int csolve_t<P>(int, int, int, double *, int, double *, double *, void *, int *, hipStream_t);
+
+}  // namespace mdls_impl

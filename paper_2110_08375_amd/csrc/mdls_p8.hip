@@ -1,8 +1,9 @@
 // mdls_p8.hip -- kernels and drivers instantiated for 8-limb numbers.
-#include "mdls_impl.hpp"
+#include "mdls_cplx.hpp"
 
 namespace mdls_impl {
 MDLS_FOR_PRECISION(extern, 2)  // the refined solve factors in double double (mdls_p2.hip)
 MDLS_FOR_PRECISION(, 8)
 MDLS_REFINE_FOR_PRECISION(, 8)
+MDLS_CPLX_FOR_PRECISION(, 8)
 }  // namespace mdls_impl

@@ -22,7 +22,8 @@ EXPORTS = ("mdls_max_rows", "mdls_workspace_bytes", "mdls_qr", "mdls_apply_qt", 
            "mdls_backsub", "mdls_solve", "mdls_status_string", "mdls_timing_enable", "mdls_timing_reset",
            "mdls_timing_query", "mdls_timing_kernels", "mdls_batch_workspace_bytes", "mdls_batch_plan",
            "mdls_solve_batched", "mdls_batch_variants", "mdls_batch_autotune", "mdls_wall_clock_khz",
-           "mdls_refined_workspace_bytes", "mdls_solve_refined", "mdls_apply_q", "mdls_form_q")
+           "mdls_refined_workspace_bytes", "mdls_solve_refined", "mdls_apply_q", "mdls_form_q",
+           "mdls_cworkspace_bytes", "mdls_cqr", "mdls_capply_qh", "mdls_cbacksub", "mdls_csolve")
 
 
 class BatchDesc(ctypes.Structure):
@@ -75,7 +76,13 @@ def lib():
         L.mdls_refined_workspace_bytes.argtypes = [i, i, i, i]
         L.mdls_refined_workspace_bytes.restype = sz
         L.mdls_solve_refined.argtypes = [i, i, i, i, vp, i, vp, vp, i, vp, vp, sz, vp, vp, vp]
-        for f in ("mdls_qr", "mdls_apply_qt", "mdls_apply_q", "mdls_form_q", "mdls_form_w", "mdls_backsub",
+        L.mdls_cworkspace_bytes.argtypes = [i, i, i, i]
+        L.mdls_cworkspace_bytes.restype = sz
+        L.mdls_cqr.argtypes = [i, i, i, i, vp, i, vp, i, vp, sz, vp]
+        L.mdls_capply_qh.argtypes = [i, i, i, i, vp, i, vp, i, vp, i, i, vp, sz, vp]
+        L.mdls_cbacksub.argtypes = [i, i, i, vp, i, vp, vp, sz, vp, vp]
+        L.mdls_csolve.argtypes = [i, i, i, i, vp, i, vp, vp, vp, sz, vp, vp]
+        for f in ("mdls_cqr", "mdls_capply_qh", "mdls_cbacksub", "mdls_csolve", "mdls_qr", "mdls_apply_qt", "mdls_apply_q", "mdls_form_q", "mdls_form_w", "mdls_backsub",
                   "mdls_solve", "mdls_timing_enable", "mdls_timing_reset", "mdls_timing_query", "mdls_timing_kernels",
                   "mdls_batch_plan", "mdls_solve_batched", "mdls_batch_variants", "mdls_batch_autotune",
                   "mdls_wall_clock_khz", "mdls_solve_refined"):
@@ -233,6 +240,104 @@ def solve(p: int, A, b, tile: int, x=None, ws=None, info=None):
     rc = lib().mdls_solve(p, m, n, tile, _ptr(A), m, _ptr(b), _ptr(x), _ptr(ws), ws.numel(), _ptr(info),
                           _stream())
     _check(rc, "mdls_solve")
+    return x, info
+
+
+# ------------------------------------------------------------------------------ complex
+# A complex matrix is a contiguous float64 tensor of shape (2, P, cols, rows): the P limb
+# planes of the real parts, then those of the imaginary parts.  A complex vector: (2, P, n).
+def _cmat(t, P, name):
+    import torch
+
+    if t.dtype != torch.float64 or not t.is_contiguous() or t.dim() != 4 or t.shape[0] != 2 or t.shape[1] != P:
+        raise ValueError("%s must be a contiguous float64 tensor of shape (2, P, cols, rows)" % name)
+    if not t.is_cuda:
+        raise ValueError("%s must live on the GPU" % name)
+    return t.shape[3], t.shape[2]  # rows (= ld), cols
+
+
+def _cvec(t, P, name, length):
+    import torch
+
+    if (t.dtype != torch.float64 or not t.is_contiguous() or t.dim() != 3 or t.shape[0] != 2 or t.shape[1] != P
+            or t.shape[2] != length or not t.is_cuda):
+        raise ValueError("%s must be a contiguous float64 GPU tensor of shape (2, %d, %d)" % (name, P, length))
+
+
+def cworkspace_bytes(p: int, m: int, n: int, tile: int) -> int:
+    return lib().mdls_cworkspace_bytes(p, m, n, tile)
+
+
+def cworkspace(p: int, m: int, n: int, tile: int, device="cuda"):
+    import torch
+
+    nb = cworkspace_bytes(p, m, n, tile)
+    if nb == 0:
+        raise ValueError("invalid sizes for a workspace")
+    return torch.empty(nb, dtype=torch.uint8, device=device)
+
+
+def cqr(p: int, A, tile: int, T=None, ws=None):
+    """In-place complex QR of A (2, P, n, m); T (2, P, n, ldt) or None receives the T_k."""
+    m, n = _cmat(A, p, "A")
+    if ws is None:
+        ws = cworkspace(p, m, n, tile, A.device)
+    ldt = 0
+    if T is not None:
+        ldt, tc = _cmat(T, p, "T")
+        if tc != n:
+            raise ValueError("T must have n columns")
+    rc = lib().mdls_cqr(p, m, n, tile, _ptr(A), m, _ptr(T), ldt, _ptr(ws), ws.numel(), _stream())
+    _check(rc, "mdls_cqr")
+    return A, T
+
+
+def capply_qh(p: int, A, T, B, tile: int, ws=None):
+    """B (2, P, nrhs, m) := Q^H B, in place."""
+    m, n = _cmat(A, p, "A")
+    ldt, tc = _cmat(T, p, "T")
+    if tc != n:
+        raise ValueError("T must have n columns")
+    ldb, nrhs = _cmat(B, p, "B")
+    if ws is None:
+        ws = cworkspace(p, m, n, tile, A.device)
+    rc = lib().mdls_capply_qh(p, m, n, tile, _ptr(A), m, _ptr(T), ldt, _ptr(B), ldb, nrhs, _ptr(ws), ws.numel(),
+                              _stream())
+    _check(rc, "mdls_capply_qh")
+    return B
+
+
+def cbacksub(p: int, R, x, tile: int, ws=None, info=None):
+    """Solve R x = y for the complex n x n upper triangle of R (2, P, n, ldr); x (2, P, n)
+    holds y on entry.  Returns (x, info tensor)."""
+    import torch
+
+    ldr, n = _cmat(R, p, "R")
+    _cvec(x, p, "x", n)
+    if ws is None:
+        ws = cworkspace(p, n, n, tile, R.device)
+    if info is None:
+        info = torch.zeros(1, dtype=torch.int32, device=R.device)
+    rc = lib().mdls_cbacksub(p, n, tile, _ptr(R), ldr, _ptr(x), _ptr(ws), ws.numel(), _ptr(info), _stream())
+    _check(rc, "mdls_cbacksub")
+    return x, info
+
+
+def csolve(p: int, A, b, tile: int, x=None, ws=None, info=None):
+    """Complex least squares: A (2, P, n, m) and b (2, P, m) are overwritten; returns (x, info)."""
+    import torch
+
+    m, n = _cmat(A, p, "A")
+    _cvec(b, p, "b", m)
+    if x is None:
+        x = torch.empty((2, p, n), dtype=torch.float64, device=A.device)
+    _cvec(x, p, "x", n)
+    if ws is None:
+        ws = cworkspace(p, m, n, tile, A.device)
+    if info is None:
+        info = torch.zeros(1, dtype=torch.int32, device=A.device)
+    rc = lib().mdls_csolve(p, m, n, tile, _ptr(A), m, _ptr(b), _ptr(x), _ptr(ws), ws.numel(), _ptr(info), _stream())
+    _check(rc, "mdls_csolve")
     return x, info
 
 

@@ -143,3 +143,53 @@ def test_explicit_q_entry_point_errors(L):
     assert L.mdls_form_q(4, 64, 32, 16, d, 64, d, 16, d, 63, 64, d, ws, None) == -10
     assert L.mdls_form_q(4, 64, 32, 16, d, 64, d, 16, d, 64, 65, d, ws, None) == -11
     assert L.mdls_form_q(4, 64, 32, 16, d, 64, d, 16, d, 64, 64, d, ws - 1, None) == -13
+
+
+def test_complex_entry_point_errors(L):
+    d = ctypes.c_void_p(16)
+    ws = L.mdls_cworkspace_bytes(2, 64, 32, 16)
+    assert ws > 0
+    assert L.mdls_cworkspace_bytes(3, 64, 32, 16) == 0
+    assert L.mdls_cworkspace_bytes(2, 16, 32, 16) == 0
+    # the complex workspace holds twice the planes of the real one's blocks
+    assert ws >= 2 * 8 * 2 * 16 * 32
+    s = L.mdls_csolve
+    assert s(5, 64, 32, 16, d, 64, d, d, d, ws, d, None) == -1
+    assert s(2, 0, 32, 16, d, 64, d, d, d, ws, d, None) == -2
+    assert s(2, 64, 65, 16, d, 64, d, d, d, ws, d, None) == -3
+    assert s(2, 64, 32, 12, d, 64, d, d, d, ws, d, None) == -4
+    assert s(2, 64, 32, 16, None, 64, d, d, d, ws, d, None) == -5
+    assert s(2, 64, 32, 16, d, 63, d, d, d, ws, d, None) == -6
+    assert s(2, 64, 32, 16, d, 64, None, d, d, ws, d, None) == -7
+    assert s(2, 64, 32, 16, d, 64, d, None, d, ws, d, None) == -8
+    assert s(2, 64, 32, 16, d, 64, d, d, None, ws, d, None) == -9
+    assert s(2, 64, 32, 16, d, 64, d, d, d, ws - 1, d, None) == -10
+    assert s(2, 64, 32, 16, d, 64, d, d, d, ws, None, None) == -11
+    q = L.mdls_cqr
+    assert q(2, 64, 32, 12, d, 64, None, 0, d, ws, None) == -4
+    assert q(2, 64, 32, 16, d, 64, d, 15, d, ws, None) == -8
+    assert q(2, 64, 32, 16, d, 64, None, 0, d, ws - 1, None) == -10
+    a = L.mdls_capply_qh
+    assert a(2, 64, 32, 16, d, 64, None, 16, d, 64, 1, d, ws, None) == -7
+    assert a(2, 64, 32, 16, d, 64, d, 16, d, 63, 1, d, ws, None) == -10
+    assert a(2, 64, 32, 16, d, 64, d, 16, d, 64, -1, d, ws, None) == -11
+    assert a(2, 64, 32, 16, d, 64, d, 16, d, 64, 0, d, ws, None) == 0  # nothing to do
+    wsb = L.mdls_cworkspace_bytes(4, 32, 32, 16)
+    b = L.mdls_cbacksub
+    assert b(4, 32, 12, d, 32, d, d, wsb, d, None) == -3
+    assert b(4, 32, 16, d, 31, d, d, wsb, d, None) == -5
+    assert b(4, 32, 16, d, 32, d, d, wsb - 1, d, None) == -8
+    assert b(4, 32, 16, d, 32, d, d, wsb, None, None) == -9
+
+
+def test_complex_binding_refuses_bad_tensors(L):
+    import torch
+
+    from paper_2110_08375_amd import mdls
+
+    A = torch.zeros((2, 2, 16, 32), dtype=torch.float64)
+    b = torch.zeros((2, 2, 32), dtype=torch.float64)
+    with pytest.raises(ValueError):
+        mdls.csolve(2, A, b, 16)  # CPU tensors
+    with pytest.raises(ValueError):
+        mdls.cqr(2, torch.zeros((2, 16, 32), dtype=torch.float64), 16)  # real layout
