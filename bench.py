@@ -208,6 +208,66 @@ def precision_run(M, dev, n=2048, tile=128):
     return out
 
 
+# Paper, Table 5 (V100, complex double double QR of a 512 x 512 matrix): kernel time in ms
+# for the tiles 16 x 32, 8 x 64, 4 x 128 and 2 x 256
+PAPER_TABLE5_COMPLEX_KERNEL_MS = {32: 97.4, 64: 227.4, 128: 238.5, 256: 420.8}
+
+
+def complex_run(M, dev, n=512):
+    """The paper's complex workload (Table 5): QR of a complex 512 x 512 matrix in double double
+    for the four tile sizes, plus the complex least-squares solve at tile 128 and the qd/od QR
+    at tile 128; each timed as the median of 3 eager calls on resident inputs."""
+    import torch
+
+    import mdgen
+    from paper_2110_08375_amd import opcount
+
+    def timed(fn, reset, reps=3):
+        ms = []
+        for _ in range(reps + 1):
+            reset()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        return sorted(ms[1:])[len(ms[1:]) // 2]
+
+    out = {"workload": "complex QR (and least squares) of a square %d x %d matrix, entries with uniform "
+                       "real and imaginary parts as the n = 1024 problem" % (n, n),
+           "unit": "ms",
+           "flops": "Table-1 double operations of the complex QR = 4 x the real QR count"}
+    for P, tiles in ((2, (32, 64, 128, 256)), (4, (128,)), (8, (128,))):
+        A0 = mdgen.cmd_uniform(P, n, n, 5000 + P, mdgen.STREAM_A, device=dev).contiguous()
+        b0 = mdgen.cmd_vector(P, n, 5000 + P, mdgen.STREAM_B, device=dev).contiguous()
+        A, b = A0.clone(), b0.clone()
+        rec = {}
+        for tile in tiles:
+            ws = M.cworkspace(P, n, n, tile, dev)
+            T = torch.zeros((2, P, n, tile), dtype=torch.float64, device=dev)
+            ms = timed(lambda: M.cqr(P, A, tile, T=T, ws=ws), lambda: A.copy_(A0))
+            r = {"qr_ms": round(ms, 3),
+                 "qr_tflops": round(opcount.cqr_double_ops(P, n, n) / (ms * 1e-3) / 1e12, 4)}
+            if P == 2:
+                r["paper_v100_kernel_ms"] = PAPER_TABLE5_COMPLEX_KERNEL_MS[tile]
+            if tile == 128:
+                x = torch.empty((2, P, n), dtype=torch.float64, device=dev)
+                info = torch.zeros(1, dtype=torch.int32, device=dev)
+
+                def reset():
+                    A.copy_(A0)
+                    b.copy_(b0)
+
+                r["solve_ms"] = round(timed(lambda: M.csolve(P, A, b, tile, x=x, ws=ws, info=info), reset), 3)
+            rec["tile%d" % tile] = r
+            log("complex %s n=%d tile %d: QR %.3f ms" % (PNAME[P], n, tile, ms))
+        out[PNAME[P]] = rec
+        del A0, b0, A, b
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -223,6 +283,7 @@ def main():
     ap.add_argument("--no-graph", action="store_true", help="time eager launches instead of a captured graph")
     ap.add_argument("--batch", type=int, default=512)
     ap.add_argument("--no-precision", action="store_true", help="skip the refined (precision-form) measurement")
+    ap.add_argument("--no-complex", action="store_true", help="skip the complex (Table 5) measurement")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -369,6 +430,7 @@ def main():
             batched[PNAME[P]] = batched_run(M, P, args.batch, 4000 + P, dev, 3, True)
 
     precision = None if args.no_precision else precision_run(M, dev)
+    cplx = None if args.no_complex else complex_run(M, dev)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -401,6 +463,7 @@ def main():
         "cpu_baseline": cpu,
         "batched": batched,
         "precision_form": precision,
+        "complex": cplx,
     }
     print(json.dumps(out), flush=True)
 

@@ -236,7 +236,7 @@ struct CPanelArgs {
 // The reflector of column c (rows c..m-1), formed by one whole workgroup: beta_c, v below the
 // diagonal, R_cc on it.
 template <int P>
-__device__ void c_reflector(double *A, long lda, long ps, int m, int c, double *beta, long bps, double *sred)
+__device__ __forceinline__ void c_reflector(double *A, long lda, long ps, int m, int c, double *beta, long bps, double *sred)
 {
     const int tid = threadIdx.x;
     const long off = (long)c * lda;
@@ -320,26 +320,24 @@ __global__ __launch_bounds__(kThreads) void k_cstep(CPanelArgs g)
 }
 
 // G(l, j) = y_l^H y_j for l < j (zero for l >= j) of the block Y (h rows, tile columns);
-// workgroup j, one wave per l.
+// one wave per (l, j): workgroup (lb, j) holds l = lb * 4 .. lb * 4 + 3.
 template <int P>
 __global__ __launch_bounds__(kThreads) void k_cgram(const double *Y, long lda, long ps, int h, int tile, double *G,
                                                    long gps)
 {
-    const int j = blockIdx.x;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    for (int l = wid; l < tile; l += kThreads / 64) {
-        if (l >= j) {
-            if (lane == 0) cstm(G, gps, (long)j * tile + l, czero<P>());
-            continue;
-        }
-        CAcc<P> acc = cacc_zero<P>();
-        int nt = 0;
-        for (int r = j + lane; r < h; r += 64)  // y_j is zero above row j
-            cacc_fma_step<P, true>(acc, cy_entry<P>(Y, lda, ps, r, l, h, tile), cy_entry<P>(Y, lda, ps, r, j, h, tile),
-                                   nt++);
-        const CV<P> s = cwave_sum(cacc_get(acc));
-        if (lane == 0) cstm(G, gps, (long)j * tile + l, s);
+    const int l = blockIdx.x * (kThreads / 64) + wid, j = blockIdx.y;
+    if (l >= tile) return;
+    if (l >= j) {
+        if (lane == 0) cstm(G, gps, (long)j * tile + l, czero<P>());
+        return;
     }
+    CAcc<P> acc = cacc_zero<P>();
+    int nt = 0;
+    for (int r = j + lane; r < h; r += 64)  // y_j is zero above row j
+        cacc_fma_step<P, true>(acc, cy_entry<P>(Y, lda, ps, r, l, h, tile), cy_entry<P>(Y, lda, ps, r, j, h, tile), nt++);
+    const CV<P> s = cwave_sum(cacc_get(acc));
+    if (lane == 0) cstm(G, gps, (long)j * tile + l, s);
 }
 
 // ============================================================================ triangular inverse
@@ -501,10 +499,11 @@ __global__ __launch_bounds__(kThreads) void k_cbs_upd(const double *Rc, long ldr
 }
 
 // ============================================================================ host side
-// columns per workgroup of k_cinvert: keeps the RPT complex row values of a thread in
-// registers (RPT = tile rows / row groups)
+// columns per workgroup of k_cinvert: each step of the serial row sweep costs a thread RPT
+// complex multiply-adds (RPT = columns per workgroup), so one column per workgroup keeps the
+// chain shortest and spreads a tile over tile workgroups
 template <int P>
-constexpr int kCInvCols = (P <= 2) ? 16 : (P == 4 ? 8 : 4);
+constexpr int kCInvCols = 1;
 
 struct CLayout {
     size_t beta, T, G, S, U, y, total;
@@ -585,8 +584,8 @@ int cqr_t(int m, int n, int tile, double *A, int lda, double *T, int ldt, void *
                         dim3(jend - j - 1), dim3(kThreads), s, pa);
         }
         const double *Y = A + (long)kt * lda + kt;
-        MDLS_LAUNCH("k_cgram", P, 2.0 * h * tile * tile, (k_cgram<P>), dim3(tile), dim3(kThreads), s, Y, (long)lda, psa, h,
-                    tile, G, gps);
+        MDLS_LAUNCH("k_cgram", P, 2.0 * h * tile * tile, (k_cgram<P>), dim3((tile + 3) / 4, tile), dim3(kThreads), s, Y,
+                    (long)lda, psa, h, tile, G, gps);
         InvArgs ia;
         ia.U = G;
         ia.ldu = tile;

@@ -46,6 +46,15 @@ def backsub_double_ops(p: int, n: int) -> float:
     return (wa + wm) * n * (n - 1) / 2.0 + n * wd
 
 
+def cqr_double_ops(p: int, m: int, n: int) -> float:
+    """Complex Householder QR of an m x n matrix: a complex multiply-add is four real ones
+    (4 multiplications, 4 additions), so four times the real count (m n^2 - n^3/3 md
+    multiply-adds and 2 n divisions); the paper gives the same factor of about four for
+    complex data (Section 4, before Table 5)."""
+    wa, wm, wd = weights(p)
+    return 4.0 * ((wa + wm) * (m * n * n - n ** 3 / 3.0) + 2.0 * n * wd)
+
+
 def md_fma_double_ops(p: int) -> int:
     wa, wm, _ = weights(p)
     return wa + wm
