@@ -19,7 +19,8 @@
 //   k_cstep   -- for panel column j: H_j applied to the panel columns right of j, one
 //                workgroup per column; workgroup 0 then forms the reflector of column j+1
 //                from the column it has just updated, so one launch per column carries the
-//                panel's serial chain;
+//                panel's serial chain (k_cstep_r: the same with the rows in registers, for
+//                columns of up to 4 x 256 rows in dd and qd);
 //   k_cgram   -- G = Y^H Y (strictly upper part) of the panel;
 //   k_cinvert -- T = (diag(1/beta) + triu(G, 1))^{-1} column-parallel, with the diagonal of
 //                the inverse supplied as beta (so beta_j = 0 gives a zero row and column, the
@@ -319,6 +320,88 @@ __global__ __launch_bounds__(kThreads) void k_cstep(CPanelArgs g)
     }
 }
 
+// k_cstep with the rows in registers: thread t holds rows j + t + q * kThreads (q < QM) of
+// columns j and c, so each is read once; the reflector of column j + 1 (workgroup 0) comes
+// from the updated registers, x1 passing through LDS with the reduction's barriers.
+// Requires m - j <= QM * kThreads.
+template <int P, int QM>
+__global__ __launch_bounds__(kThreads) void k_cstep_r(CPanelArgs g)
+{
+    __shared__ double sred[(kThreads / 64) * 2 * P];
+    __shared__ double sx1[2 * P];
+    const int c = g.j + 1 + blockIdx.x;
+    const int tid = threadIdx.x;
+    const long offj = (long)g.j * g.lda, offc = (long)c * g.lda;
+    const V<P> bt = ldm<P>(g.beta, g.bps, g.j);
+    CV<P> a[QM], v[QM];
+#pragma unroll
+    for (int q = 0; q < QM; ++q) {
+        const long r = g.j + tid + (long)q * kThreads;
+        const bool in = r < g.m;
+        a[q] = in ? cldm<P>(g.A, g.ps, offc + r) : czero<P>();
+        v[q] = (in && r > g.j) ? cldm<P>(g.A, g.ps, offj + r) : ((r == g.j) ? cone<P>() : czero<P>());
+    }
+    if (!is_zero(bt)) {
+        CAcc<P> acc = cacc_zero<P>();
+#pragma unroll
+        for (int q = 0; q < QM; ++q) cacc_fma_step<P, true>(acc, v[q], a[q], q);
+        const CV<P> w = cblock_sum(cacc_get(acc), sred);  // v^H a_c
+        const CV<P> nt_ = cneg(cscale(w, bt));
+#pragma unroll
+        for (int q = 0; q < QM; ++q) {
+            const long r = g.j + tid + (long)q * kThreads;
+            CAcc<P> t = cacc_from(a[q]);
+            cacc_fma<P, false>(t, v[q], nt_);
+            a[q] = cacc_get(t);
+            if (r < g.m) cstm(g.A, g.ps, offc + r, a[q]);
+        }
+    }
+    if (blockIdx.x != 0) return;  // uniform per workgroup
+    // the reflector of column c = j + 1: x1 is row c (thread 1, q = 0), x below it
+    if (tid == 1) clds_st(sx1, a[0]);
+    Acc<P> sacc = acc_zero<P>();
+#pragma unroll
+    for (int q = 0; q < QM; ++q) {
+        const long r = g.j + tid + (long)q * kThreads;
+        if (r > c && r < g.m) {
+            acc_fma(sacc, a[q].re, a[q].re);
+            acc_fma(sacc, a[q].im, a[q].im);
+            if (((q + 1) % kCLazy<P>) == 0) sacc = acc_from(acc_get(sacc));
+        }
+    }
+    const V<P> sig = rblock_sum(acc_get(sacc), sred);  // its barriers publish sx1
+    if (is_zero(sig)) {
+        if (tid == 0) stm(g.beta, g.bps, c, zero<P>());
+        return;
+    }
+    const CV<P> alpha = clds_ld<P>(sx1);
+    const V<P> a2 = cabs2(alpha);
+    const V<P> mu = sqrt_md(add(a2, sig));
+    const V<P> rho = sqrt_md(a2);
+    CV<P> ph;
+    V<P> nu;
+    if (is_zero(rho)) {
+        ph = cone<P>();
+        nu = neg(mu);
+    } else {
+        const V<P> ir = recip(rho);
+        ph = CV<P>{mul(alpha.re, ir), mul(alpha.im, ir)};
+        nu = neg(div(sig, add(rho, mu)));
+    }
+    const V<P> nu2 = mul(nu, nu);
+    const V<P> btc = div(scale(nu2, 2.0), add(sig, nu2));
+    const CV<P> iv = crecip(cscale(ph, nu));  // 1 / v1
+#pragma unroll
+    for (int q = 0; q < QM; ++q) {
+        const long r = g.j + tid + (long)q * kThreads;
+        if (r > c && r < g.m) cstm(g.A, g.ps, offc + r, cmul(a[q], iv));
+    }
+    if (tid == 1) {
+        stm(g.beta, g.bps, c, btc);
+        cstm(g.A, g.ps, offc + c, cscale(ph, mu));
+    }
+}
+
 // G(l, j) = y_l^H y_j for l < j (zero for l >= j) of the block Y (h rows, tile columns);
 // one wave per (l, j): workgroup (lb, j) holds l = lb * 4 .. lb * 4 + 3.
 template <int P>
@@ -580,8 +663,23 @@ int cqr_t(int m, int n, int tile, double *A, int lda, double *T, int ldt, void *
         MDLS_LAUNCH("k_crefl", P, 6.0 * h, (k_crefl<P>), dim3(1), dim3(kThreads), s, pa);
         for (int j = kt; j < jend - 1; ++j) {
             pa.j = j;
-            MDLS_LAUNCH("k_cstep", P, 8.0 * (m - j) * (jend - j - 1) + 6.0 * (m - j - 1), (k_cstep<P>),
-                        dim3(jend - j - 1), dim3(kThreads), s, pa);
+            const int hj = m - j;
+            const double work = 8.0 * hj * (jend - j - 1) + 6.0 * (hj - 1);
+            const dim3 grid(jend - j - 1);
+            // register-resident rows where they fit without spilling (P <= 4)
+            bool done = false;
+            if constexpr (P <= 4) {
+                done = true;
+                if (hj <= kThreads)
+                    MDLS_LAUNCH("k_cstep", P, work, (k_cstep_r<P, 1>), grid, dim3(kThreads), s, pa);
+                else if (hj <= 2 * kThreads)
+                    MDLS_LAUNCH("k_cstep", P, work, (k_cstep_r<P, 2>), grid, dim3(kThreads), s, pa);
+                else if (hj <= 4 * kThreads)
+                    MDLS_LAUNCH("k_cstep", P, work, (k_cstep_r<P, 4>), grid, dim3(kThreads), s, pa);
+                else
+                    done = false;
+            }
+            if (!done) MDLS_LAUNCH("k_cstep", P, work, (k_cstep<P>), grid, dim3(kThreads), s, pa);
         }
         const double *Y = A + (long)kt * lda + kt;
         MDLS_LAUNCH("k_cgram", P, 2.0 * h * tile * tile, (k_cgram<P>), dim3((tile + 3) / 4, tile), dim3(kThreads), s, Y,

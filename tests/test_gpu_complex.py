@@ -80,6 +80,8 @@ CASES = [
     (2, 128, 128, 32),   # square, 4 tiles, sigma = 0 in the last column
     (2, 200, 96, 32),    # tall
     (2, 300, 64, 16),    # more rows than threads per workgroup, ragged
+    (2, 700, 40, 8),     # column steps with 3-4 rows per thread in registers
+    (4, 1100, 32, 16),   # columns taller than the register-resident step (loop path)
     (2, 40, 24, 8),
     (4, 96, 64, 16),
     (4, 70, 70, 14),
