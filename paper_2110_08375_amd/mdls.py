@@ -208,12 +208,14 @@ def form_w(p: int, A, T, tile: int, W):
 
 
 def backsub(p: int, R, x, tile: int, n: int | None = None, ws=None, info=None):
-    """Solve R(0:n,0:n) x = y; x (P, n) holds y on entry.  Returns (x, info tensor)."""
+    """Solve R x = y for the n x n upper triangle of R (P, n, ldr); x (P, n) holds y on entry.
+    Returns (x, info tensor).  The library takes R's plane stride as ldr * n, so R must have
+    exactly n columns."""
     import torch
 
-    ldr, cols = _mat(R, p, "R")
-    if n is None:
-        n = cols
+    if n is not None and R.dim() == 3 and n != R.shape[1]:
+        raise ValueError("R must have exactly n columns (its limb planes are ldr * n apart)")
+    ldr, n = _mat(R, p, "R")
     _vec(x, p, "x", n)
     if ws is None:
         ws = workspace(p, n, n, tile, R.device)

@@ -193,3 +193,14 @@ def test_complex_binding_refuses_bad_tensors(L):
         mdls.csolve(2, A, b, 16)  # CPU tensors
     with pytest.raises(ValueError):
         mdls.cqr(2, torch.zeros((2, 16, 32), dtype=torch.float64), 16)  # real layout
+
+
+def test_backsub_binding_requires_n_columns(L):
+    import torch
+
+    from paper_2110_08375_amd import mdls
+
+    R = torch.zeros((2, 64, 64), dtype=torch.float64)
+    x = torch.zeros((2, 32), dtype=torch.float64)
+    with pytest.raises(ValueError, match="exactly n columns"):
+        mdls.backsub(2, R, x, 16, n=32)  # planes would be misread: refused before any call
