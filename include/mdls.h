@@ -126,6 +126,22 @@ int mdls_solve(int p, int m, int n, int tile, double *A, int lda, double *b, dou
 const char *mdls_status_string(int status);
 
 /*
+ * The double-double trailing-update product S = Y^T C (the GEMM-shaped update stage of
+ * Algorithm 2, Section 3) on either execution unit, for the precision form's comparison:
+ * method 0 runs it on the FP64 vector units in double-double arithmetic; method 1 on the FP64
+ * matrix cores (MFMA) by exact slicing (Ozaki, Ogita, Oishi and Rump 2012): every column of Y
+ * and C is scaled by a power of two, every entry cut into 7 slices of at most 19 bits, and
+ * the slice products summed exactly in FP64 by level, then renormalised to double double
+ * (normwise error below 2^-104 of max|Y| max|C| h).  Y is h x w (2 planes of ldy x w), C is
+ * h x c (2 planes of ldc x c), S is w x c (2 planes of lds x c).  Method 1 needs h <= 1024
+ * (the exactness bound), w <= 16, and a workspace of mdls_dd_gemm_tn_workspace_bytes(w, c)
+ * bytes; method 0 needs none (ws may be NULL).  Status -1..-12 for arguments 1..12.
+ */
+size_t mdls_dd_gemm_tn_workspace_bytes(int w, int c);
+int mdls_dd_gemm_tn(int method, int h, int w, int c, const double *Y, int ldy, const double *C,
+                    int ldc, double *S, int lds, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/*
  * Complex least squares (the paper's complex workload: Section 3 replaces the transpose of
  * Algorithm 2 by the Hermitian transpose; Section 4, Table 5 times the complex double
  * double QR).  A complex matrix is 2P planes: the P limb planes of the real parts, then the

@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "mdls_cplx.hpp"
+#include "mdls_split.hpp"
 
 namespace mdls_impl {
 MDLS_FOR_PRECISION(extern, 1)
@@ -318,6 +319,30 @@ int mdls_backsub(int p, int n, int tile, const double *R, int ldr, double *x, vo
     if (ws_bytes < mdls_workspace_bytes(p, n, n, tile)) return -8;
     if (!d_info) return -9;
     return dispatch<BacksubF>(p, n, tile, R, ldr, x, ws, d_info, stream);
+}
+
+size_t mdls_dd_gemm_tn_workspace_bytes(int w, int c)
+{
+    if (w < 1 || w > 16 || c < 1) return 0;
+    return split_workspace_bytes(w, c);
+}
+
+int mdls_dd_gemm_tn(int method, int h, int w, int c, const double *Y, int ldy, const double *C, int ldc, double *S,
+                    int lds, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    if (method != 0 && method != 1) return -1;
+    if (h < 1 || (method == 1 && h > kSplitMaxRows)) return -2;
+    if (w < 1 || (method == 1 && w > 16)) return -3;
+    if (c < 1) return -4;
+    if (!Y) return -5;
+    if (ldy < h) return -6;
+    if (!C) return -7;
+    if (ldc < h) return -8;
+    if (!S) return -9;
+    if (lds < w) return -10;
+    if (method == 1 && !ws) return -11;
+    if (method == 1 && ws_bytes < split_workspace_bytes(w, c)) return -12;
+    return dd_gemm_tn(method, h, w, c, Y, ldy, C, ldc, S, lds, ws, stream);
 }
 
 size_t mdls_cworkspace_bytes(int p, int m, int n, int tile)

@@ -23,7 +23,8 @@ EXPORTS = ("mdls_max_rows", "mdls_workspace_bytes", "mdls_qr", "mdls_apply_qt", 
            "mdls_timing_query", "mdls_timing_kernels", "mdls_batch_workspace_bytes", "mdls_batch_plan",
            "mdls_solve_batched", "mdls_batch_variants", "mdls_batch_autotune", "mdls_wall_clock_khz",
            "mdls_refined_workspace_bytes", "mdls_solve_refined", "mdls_apply_q", "mdls_form_q",
-           "mdls_cworkspace_bytes", "mdls_cqr", "mdls_capply_qh", "mdls_cbacksub", "mdls_csolve")
+           "mdls_cworkspace_bytes", "mdls_cqr", "mdls_capply_qh", "mdls_cbacksub", "mdls_csolve",
+           "mdls_dd_gemm_tn_workspace_bytes", "mdls_dd_gemm_tn")
 
 
 class BatchDesc(ctypes.Structure):
@@ -82,7 +83,10 @@ def lib():
         L.mdls_capply_qh.argtypes = [i, i, i, i, vp, i, vp, i, vp, i, i, vp, sz, vp]
         L.mdls_cbacksub.argtypes = [i, i, i, vp, i, vp, vp, sz, vp, vp]
         L.mdls_csolve.argtypes = [i, i, i, i, vp, i, vp, vp, vp, sz, vp, vp]
-        for f in ("mdls_cqr", "mdls_capply_qh", "mdls_cbacksub", "mdls_csolve", "mdls_qr", "mdls_apply_qt", "mdls_apply_q", "mdls_form_q", "mdls_form_w", "mdls_backsub",
+        L.mdls_dd_gemm_tn_workspace_bytes.argtypes = [i, i]
+        L.mdls_dd_gemm_tn_workspace_bytes.restype = sz
+        L.mdls_dd_gemm_tn.argtypes = [i, i, i, i, vp, i, vp, i, vp, i, vp, sz, vp]
+        for f in ("mdls_dd_gemm_tn", "mdls_cqr", "mdls_capply_qh", "mdls_cbacksub", "mdls_csolve", "mdls_qr", "mdls_apply_qt", "mdls_apply_q", "mdls_form_q", "mdls_form_w", "mdls_backsub",
                   "mdls_solve", "mdls_timing_enable", "mdls_timing_reset", "mdls_timing_query", "mdls_timing_kernels",
                   "mdls_batch_plan", "mdls_solve_batched", "mdls_batch_variants", "mdls_batch_autotune",
                   "mdls_wall_clock_khz", "mdls_solve_refined"):
@@ -243,6 +247,28 @@ def solve(p: int, A, b, tile: int, x=None, ws=None, info=None):
                           _stream())
     _check(rc, "mdls_solve")
     return x, info
+
+
+def dd_gemm_tn(method: int, Y, C, S=None, ws=None):
+    """S (2, c, w) := Y^T C for double-double Y (2, w, h) and C (2, c, h): method 0 on the
+    vector units, 1 on the matrix cores by exact slicing."""
+    import torch
+
+    h, w = _mat(Y, 2, "Y")
+    hc, c = _mat(C, 2, "C")
+    if hc != h:
+        raise ValueError("Y and C need the same number of rows")
+    if S is None:
+        S = torch.empty((2, c, w), dtype=torch.float64, device=Y.device)
+    lds, sc = _mat(S, 2, "S")
+    if sc != c:
+        raise ValueError("S must have c columns")
+    if ws is None and method == 1:
+        ws = torch.empty(lib().mdls_dd_gemm_tn_workspace_bytes(w, c), dtype=torch.uint8, device=Y.device)
+    rc = lib().mdls_dd_gemm_tn(method, h, w, c, _ptr(Y), h, _ptr(C), h, _ptr(S), lds, _ptr(ws),
+                               0 if ws is None else ws.numel(), _stream())
+    _check(rc, "mdls_dd_gemm_tn")
+    return S
 
 
 # ------------------------------------------------------------------------------ complex
