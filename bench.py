@@ -298,8 +298,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the design for sharding is described in DESIGN.md); run with --gpus 1",
+        print("bench.py measures one GPU only: the library has no multi-GPU path; run with --gpus 1",
               file=sys.stderr)
         sys.exit(2)
 

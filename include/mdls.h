@@ -45,7 +45,7 @@ extern "C" {
 typedef enum { MDLS_F64 = 1, MDLS_DD = 2, MDLS_QD = 4, MDLS_OD = 8 } mdls_prec;
 
 #define MDLS_EHIP (-100)        /* a kernel launch failed */
-#define MDLS_EUNSUPPORTED (-101) /* valid arguments outside what this build handles */
+#define MDLS_EUNSUPPORTED (-101) /* valid arguments outside what the library handles */
 
 /* Largest number of rows the Householder panel kernel holds on chip, for precision p. */
 int mdls_max_rows(int p);

@@ -637,7 +637,7 @@ const char *mdls_status_string(int status)
 {
     if (status == 0) return "success";
     if (status == MDLS_EHIP) return "a HIP kernel launch failed";
-    if (status == MDLS_EUNSUPPORTED) return "arguments valid but outside what this build supports";
+    if (status == MDLS_EUNSUPPORTED) return "arguments valid but outside what the library supports";
     if (status < 0 && status > -20) return "invalid argument (the negated status is its 1-based position)";
     return "unknown status";
 }
