@@ -178,6 +178,15 @@ int mdls_capply_qh(int p, int m, int n, int tile, const double *A, int lda, cons
                    int ldt, double *B, int ldb, int nrhs, void *ws, size_t ws_bytes,
                    hipStream_t stream);
 
+/* B := Q B (the blocks in reverse, B := (I - Y_k T_k Y_k^H) B) and the first ncols columns of the
+ * explicit unitary factor (2P planes of ldq x ncols), as mdls_apply_q and mdls_form_q for real data. */
+int mdls_capply_q(int p, int m, int n, int tile, const double *A, int lda, const double *T,
+                  int ldt, double *B, int ldb, int nrhs, void *ws, size_t ws_bytes,
+                  hipStream_t stream);
+int mdls_cform_q(int p, int m, int n, int tile, const double *A, int lda, const double *T,
+                 int ldt, double *Q, int ldq, int ncols, void *ws, size_t ws_bytes,
+                 hipStream_t stream);
+
 /* Complex tiled back substitution (Algorithm 1): x (2P planes of n) holds y on entry and the
  * solution of R x = y on exit, R the upper triangle of the leading n x n block (ldr >= n). */
 int mdls_cbacksub(int p, int n, int tile, const double *R, int ldr, double *x, void *ws,

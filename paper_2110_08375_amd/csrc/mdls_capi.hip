@@ -157,6 +157,16 @@ struct CApplyF {
     static int run(A... a) { return capply_qh_t<P>(a...); }
 };
 template <int P>
+struct CApplyQF {
+    template <typename... A>
+    static int run(A... a) { return capply_q_t<P>(a...); }
+};
+template <int P>
+struct CFormQF {
+    template <typename... A>
+    static int run(A... a) { return cform_q_t<P>(a...); }
+};
+template <int P>
 struct CBacksubF {
     template <typename... A>
     static int run(A... a) { return cbacksub_t<P>(a...); }
@@ -384,6 +394,45 @@ int mdls_capply_qh(int p, int m, int n, int tile, const double *A, int lda, cons
     if (ws_bytes < mdls_cworkspace_bytes(p, m, n, tile)) return -13;
     if (nrhs == 0) return 0;
     return dispatch<CApplyF>(p, m, n, tile, A, lda, T, ldt, B, ldb, nrhs, ws, stream);
+}
+
+int mdls_capply_q(int p, int m, int n, int tile, const double *A, int lda, const double *T, int ldt, double *B,
+                  int ldb, int nrhs, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    if (!valid_p(p)) return -1;
+    if (m < 1) return -2;
+    if (n < 1 || n > m) return -3;
+    if (!valid_tile(tile) || n % tile != 0) return -4;
+    if (!A) return -5;
+    if (lda < m) return -6;
+    if (!T) return -7;
+    if (ldt < tile) return -8;
+    if (!B && nrhs > 0) return -9;
+    if (ldb < m) return -10;
+    if (nrhs < 0) return -11;
+    if (!ws) return -12;
+    if (ws_bytes < mdls_cworkspace_bytes(p, m, n, tile)) return -13;
+    if (nrhs == 0) return 0;
+    return dispatch<CApplyQF>(p, m, n, tile, A, lda, T, ldt, B, ldb, nrhs, ws, stream);
+}
+
+int mdls_cform_q(int p, int m, int n, int tile, const double *A, int lda, const double *T, int ldt, double *Q, int ldq,
+                 int ncols, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    if (!valid_p(p)) return -1;
+    if (m < 1) return -2;
+    if (n < 1 || n > m) return -3;
+    if (!valid_tile(tile) || n % tile != 0) return -4;
+    if (!A) return -5;
+    if (lda < m) return -6;
+    if (!T) return -7;
+    if (ldt < tile) return -8;
+    if (!Q) return -9;
+    if (ldq < m) return -10;
+    if (ncols < 1 || ncols > m) return -11;
+    if (!ws) return -12;
+    if (ws_bytes < mdls_cworkspace_bytes(p, m, n, tile)) return -13;
+    return dispatch<CFormQF>(p, m, n, tile, A, lda, T, ldt, Q, ldq, ncols, ws, stream);
 }
 
 int mdls_cbacksub(int p, int n, int tile, const double *R, int ldr, double *x, void *ws, size_t ws_bytes, int *d_info,

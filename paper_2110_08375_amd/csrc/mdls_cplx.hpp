@@ -27,7 +27,8 @@
 //                identity reflector); also the diagonal tiles of R for the back substitution;
 //   k_ctn, k_ctrmm_h, k_cnn_sub -- the trailing update C := (I - Y T^H Y^H) C, which is the
 //                paper's C + Y W^H C with W = -Y T, and the same for Q^H B;
-//   k_cbs_xi, k_cbs_upd -- x_i := U_i^{-1} b_i and b_j -= A_{j,i} x_i.
+//   k_cbs_xi, k_cbs_upd -- x_i := U_i^{-1} b_i and b_j -= A_{j,i} x_i;
+//   k_ctrmm_n, k_cidentity -- Q B and the explicit unitary factor (the blocks in reverse).
 #pragma once
 #include "mdls_impl.hpp"
 
@@ -521,6 +522,31 @@ __global__ __launch_bounds__(kThreads) void k_ctrmm_h(const double *T, long ldt,
     cstm(U, sps, (long)c * tile + i, cacc_get(acc));
 }
 
+// U(i, c) = sum_{l >= i} T(i, l) S(l, c), i.e. U = T S (the block reflector without the
+// Hermitian transpose, for Q B)
+template <int P>
+__global__ __launch_bounds__(kThreads) void k_ctrmm_n(const double *T, long ldt, long tps, const double *S, long sps,
+                                                     double *U, int tile, int nrhs)
+{
+    const int i = blockIdx.x * kThreads + threadIdx.x, c = blockIdx.y;
+    if (i >= tile || c >= nrhs) return;
+    CAcc<P> acc = cacc_zero<P>();
+    for (int l = i; l < tile; ++l)
+        cacc_fma_step<P, false>(acc, cldm<P>(T, tps, (long)l * ldt + i), cldm<P>(S, sps, (long)c * tile + l), l - i);
+    cstm(U, sps, (long)c * tile + i, cacc_get(acc));
+}
+
+namespace {
+// B(i, c) = 1 if i == c else 0 (2P planes)
+__global__ void k_cidentity(double *B, long ldb, long bps, int rows, int cols, int P)
+{
+    const long r = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
+    if (r >= rows || c >= cols) return;
+    for (int k = 0; k < 2 * P; ++k) B[k * bps + (long)c * ldb + r] = (k == 0 && r == c) ? 1.0 : 0.0;
+}
+}  // namespace
+
 // B(r, c) -= sum_l Y(r, l) U(l, c), r < h
 template <int P>
 __global__ __launch_bounds__(kThreads) void k_cnn_sub(const double *Y, long lda, long ps, int h, int tile, const double *U,
@@ -727,6 +753,46 @@ int capply_qh_t(int m, int n, int tile, const double *A, int lda, const double *
     return hipGetLastError() == hipSuccess ? 0 : MDLS_EHIP;
 }
 
+// B := Q B (the tile blocks in reverse order, B := (I - Y_k T_k Y_k^H) B); with B = I this forms
+// the unitary factor the paper's Algorithm 2 builds (Section 3)
+template <int P>
+int capply_q_t(int m, int n, int tile, const double *A, int lda, const double *T, int ldt, double *B, int ldb, int nrhs,
+               void *ws, hipStream_t s)
+{
+    const CLayout L = clayout(P, m, n, tile);
+    char *w = (char *)ws;
+    double *S = (double *)(w + L.S);
+    double *U = (double *)(w + L.U);
+    const long psa = (long)lda * n, tps = (long)ldt * n, bps = (long)ldb * nrhs, sps = (long)tile * L.sc;
+    const int N = n / tile;
+    for (int c0 = 0; c0 < nrhs; c0 += L.sc) {
+        const int nc = (nrhs - c0 < L.sc) ? nrhs - c0 : L.sc;
+        double *Bc = B + (long)c0 * ldb;
+        for (int k = N - 1; k >= 0; --k) {
+            const long kt = (long)k * tile;
+            const double *Y = A + kt * lda + kt;
+            const int h = m - (int)kt;
+            MDLS_LAUNCH("k_ctn", P, 4.0 * h * tile * nc, (k_ctn<P>), dim3((tile + 3) / 4, nc), dim3(kThreads), s, Y,
+                        (long)lda, psa, h, tile, Bc + kt, (long)ldb, bps, nc, S, sps);
+            MDLS_LAUNCH("k_ctrmm_n", P, 2.0 * tile * tile * nc, (k_ctrmm_n<P>), dim3((tile + kThreads - 1) / kThreads, nc),
+                        dim3(kThreads), s, T + kt * ldt, (long)ldt, tps, S, sps, U, tile, nc);
+            MDLS_LAUNCH("k_cnn_sub", P, 4.0 * h * tile * nc, (k_cnn_sub<P>), dim3((h + kThreads - 1) / kThreads, nc),
+                        dim3(kThreads), s, Y, (long)lda, psa, h, tile, U, sps, Bc + kt, (long)ldb, bps);
+        }
+    }
+    return hipGetLastError() == hipSuccess ? 0 : MDLS_EHIP;
+}
+
+// Q(:, 0:ncols) := the first ncols columns of the m x m unitary factor
+template <int P>
+int cform_q_t(int m, int n, int tile, const double *A, int lda, const double *T, int ldt, double *Q, int ldq, int ncols,
+              void *ws, hipStream_t s)
+{
+    MDLS_LAUNCH("k_cidentity", P, 0, k_cidentity, dim3((m + 255) / 256, ncols), dim3(256), s, Q, (long)ldq,
+                (long)ldq * ncols, m, ncols, P);
+    return capply_q_t<P>(m, n, tile, A, lda, T, ldt, Q, ldq, ncols, ws, s);
+}
+
 // tiled back substitution on y (2P planes of n); x receives the solution
 template <int P>
 void cbacksub_tiles(const CLayout &L, char *w, int n, int tile, const double *R, long ldr, long psr, double *y, double *x,
@@ -795,6 +861,10 @@ int csolve_t(int m, int n, int tile, double *A, int lda, double *b, double *x, v
     X template int capply_qh_t<P>(int, int, int, const double *, int, const double *, int, double *, int, int,      \
                                   void *, hipStream_t);                                                            \
     X template int cbacksub_t<P>(int, int, const double *, int, double *, void *, int *, hipStream_t);             \
+    X template int capply_q_t<P>(int, int, int, const double *, int, const double *, int, double *, int, int,       \
+                                 void *, hipStream_t);                                                             \
+    X template int cform_q_t<P>(int, int, int, const double *, int, const double *, int, double *, int, int,        \
+                                void *, hipStream_t);                                                              \
     X template int csolve_t<P>(int, int, int, double *, int, double *, double *, void *, int *, hipStream_t);
 
 }  // namespace mdls_impl

@@ -24,7 +24,7 @@ EXPORTS = ("mdls_max_rows", "mdls_workspace_bytes", "mdls_qr", "mdls_apply_qt", 
            "mdls_solve_batched", "mdls_batch_variants", "mdls_batch_autotune", "mdls_wall_clock_khz",
            "mdls_refined_workspace_bytes", "mdls_solve_refined", "mdls_apply_q", "mdls_form_q",
            "mdls_cworkspace_bytes", "mdls_cqr", "mdls_capply_qh", "mdls_cbacksub", "mdls_csolve",
-           "mdls_dd_gemm_tn_workspace_bytes", "mdls_dd_gemm_tn")
+           "mdls_dd_gemm_tn_workspace_bytes", "mdls_dd_gemm_tn", "mdls_capply_q", "mdls_cform_q")
 
 
 class BatchDesc(ctypes.Structure):
@@ -82,11 +82,13 @@ def lib():
         L.mdls_cqr.argtypes = [i, i, i, i, vp, i, vp, i, vp, sz, vp]
         L.mdls_capply_qh.argtypes = [i, i, i, i, vp, i, vp, i, vp, i, i, vp, sz, vp]
         L.mdls_cbacksub.argtypes = [i, i, i, vp, i, vp, vp, sz, vp, vp]
+        L.mdls_capply_q.argtypes = [i, i, i, i, vp, i, vp, i, vp, i, i, vp, sz, vp]
+        L.mdls_cform_q.argtypes = [i, i, i, i, vp, i, vp, i, vp, i, i, vp, sz, vp]
         L.mdls_csolve.argtypes = [i, i, i, i, vp, i, vp, vp, vp, sz, vp, vp]
         L.mdls_dd_gemm_tn_workspace_bytes.argtypes = [i, i]
         L.mdls_dd_gemm_tn_workspace_bytes.restype = sz
         L.mdls_dd_gemm_tn.argtypes = [i, i, i, i, vp, i, vp, i, vp, i, vp, sz, vp]
-        for f in ("mdls_dd_gemm_tn", "mdls_cqr", "mdls_capply_qh", "mdls_cbacksub", "mdls_csolve", "mdls_qr", "mdls_apply_qt", "mdls_apply_q", "mdls_form_q", "mdls_form_w", "mdls_backsub",
+        for f in ("mdls_capply_q", "mdls_cform_q", "mdls_dd_gemm_tn", "mdls_cqr", "mdls_capply_qh", "mdls_cbacksub", "mdls_csolve", "mdls_qr", "mdls_apply_qt", "mdls_apply_q", "mdls_form_q", "mdls_form_w", "mdls_backsub",
                   "mdls_solve", "mdls_timing_enable", "mdls_timing_reset", "mdls_timing_query", "mdls_timing_kernels",
                   "mdls_batch_plan", "mdls_solve_batched", "mdls_batch_variants", "mdls_batch_autotune",
                   "mdls_wall_clock_khz", "mdls_solve_refined"):
@@ -333,6 +335,36 @@ def capply_qh(p: int, A, T, B, tile: int, ws=None):
                               _stream())
     _check(rc, "mdls_capply_qh")
     return B
+
+
+def capply_q(p: int, A, T, B, tile: int, ws=None):
+    """B (2, P, nrhs, m) := Q B, in place."""
+    m, n = _cmat(A, p, "A")
+    ldt, tc = _cmat(T, p, "T")
+    if tc != n:
+        raise ValueError("T must have n columns")
+    ldb, nrhs = _cmat(B, p, "B")
+    if ws is None:
+        ws = cworkspace(p, m, n, tile, A.device)
+    rc = lib().mdls_capply_q(p, m, n, tile, _ptr(A), m, _ptr(T), ldt, _ptr(B), ldb, nrhs, _ptr(ws), ws.numel(),
+                             _stream())
+    _check(rc, "mdls_capply_q")
+    return B
+
+
+def cform_q(p: int, A, T, tile: int, Q, ws=None):
+    """Q (2, P, ncols, m) := the first ncols columns of the explicit unitary factor."""
+    m, n = _cmat(A, p, "A")
+    ldt, tc = _cmat(T, p, "T")
+    if tc != n:
+        raise ValueError("T must have n columns")
+    ldq, ncols = _cmat(Q, p, "Q")
+    if ws is None:
+        ws = cworkspace(p, m, n, tile, A.device)
+    rc = lib().mdls_cform_q(p, m, n, tile, _ptr(A), m, _ptr(T), ldt, _ptr(Q), ldq, ncols, _ptr(ws), ws.numel(),
+                            _stream())
+    _check(rc, "mdls_cform_q")
+    return Q
 
 
 def cbacksub(p: int, R, x, tile: int, ws=None, info=None):

@@ -204,3 +204,14 @@ def test_backsub_binding_requires_n_columns(L):
     x = torch.zeros((2, 32), dtype=torch.float64)
     with pytest.raises(ValueError, match="exactly n columns"):
         mdls.backsub(2, R, x, 16, n=32)  # planes would be misread: refused before any call
+
+
+def test_complex_explicit_q_entry_point_errors(L):
+    d = ctypes.c_void_p(16)
+    ws = L.mdls_cworkspace_bytes(2, 64, 32, 16)
+    assert L.mdls_capply_q(2, 64, 32, 12, d, 64, d, 16, d, 64, 1, d, ws, None) == -4
+    assert L.mdls_capply_q(2, 64, 32, 16, d, 64, None, 16, d, 64, 1, d, ws, None) == -7
+    assert L.mdls_capply_q(2, 64, 32, 16, d, 64, d, 16, d, 64, 1, d, ws - 1, None) == -13
+    assert L.mdls_cform_q(2, 64, 32, 16, d, 64, d, 16, None, 64, 64, d, ws, None) == -9
+    assert L.mdls_cform_q(2, 64, 32, 16, d, 64, d, 16, d, 63, 64, d, ws, None) == -10
+    assert L.mdls_cform_q(2, 64, 32, 16, d, 64, d, 16, d, 64, 65, d, ws, None) == -11

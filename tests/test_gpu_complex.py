@@ -246,3 +246,47 @@ def test_csolve_graph_replay(M, orc):
         g.replay()
         torch.cuda.synchronize()
         assert torch.equal(x, x_eager)
+
+
+@pytest.mark.parametrize("P,m,n,tile", [(2, 48, 32, 16), (4, 40, 24, 8), (8, 24, 16, 8)])
+def test_cform_q_matches_oracle(M, orc, P, m, n, tile):
+    """The explicit unitary factor (the paper's Algorithm 2 forms Q) against the oracle's."""
+    print("case cform_q P=%d m=%d n=%d tile=%d" % (P, m, n, tile), flush=True)
+    A = mdgen.cmd_uniform(P, m, n, 3700 + m, mdgen.STREAM_A)
+    Fo, beta = orc.cqr(A)
+    Qo = orc.cexplicit_q(Fo, beta)
+    Ag = to_gpu(A)
+    T = torch.zeros((2, P, n, tile), dtype=torch.float64, device=dev())
+    M.cqr(P, Ag, tile, T=T)
+    Q = torch.zeros((2, P, m, m), dtype=torch.float64, device=dev())
+    M.cform_q(P, Ag, T, tile, Q)
+    torch.cuda.synchronize()
+    bound = TOL[P] * max(1.0, kappa(A))
+    e = cerr(Q.cpu().numpy(), Qo)
+    report("Q", e, bound)
+    assert e <= bound
+
+
+def test_q_unitary_on_gpu(M):
+    """Q^H Q = I for the 256 x 256 double double case, Q formed and applied on the GPU, and
+    Q (Q^H B) = B."""
+    P, n, tile = 2, 256, 64
+    A = mdgen.cmd_uniform(P, n, n, 3800, mdgen.STREAM_A)
+    Ag = to_gpu(A)
+    T = torch.zeros((2, P, n, tile), dtype=torch.float64, device=dev())
+    M.cqr(P, Ag, tile, T=T)
+    Q = torch.zeros((2, P, n, n), dtype=torch.float64, device=dev())
+    M.cform_q(P, Ag, T, tile, Q)
+    QhQ = M.capply_qh(P, Ag, T, Q.clone(), tile)
+    B = to_gpu(mdgen.cmd_uniform(P, n, 5, 3800, mdgen.STREAM_B))
+    B2 = M.capply_q(P, Ag, T, M.capply_qh(P, Ag, T, B.clone(), tile), tile)
+    torch.cuda.synchronize()
+    I = np.zeros((2, P, n, n))
+    for i in range(n):
+        I[0, 0, i, i] = 1.0
+    e = cerr(QhQ.cpu().numpy(), I)
+    report("Q^H Q - I", e, 1e-28)
+    assert e <= 1e-28
+    e = cerr(B2.cpu().numpy(), B.cpu().numpy())
+    report("Q Q^H B - B", e, 1e-28)
+    assert e <= 1e-28
