@@ -386,8 +386,9 @@ __device__ __forceinline__ void panel_run(const PanelArgs &g, int bid)
     // Per column j the serial chain (reduction, mu, tau) runs in wave 0; the other waves do
     // the off-chain work between the same workgroup barriers:
     //   [B1, B2]  wave 0: reduction of the partial sums (and the grid exchange);
-    //             wave 2: beta of column j-1; wave 3: g(l, j-1) (block 0 only)
-    //   [B2, M]   wave 0: mu; wave 1: A_c; wave 2: 1/sigma; wave 3: w = T(:, :j-1) g(:, j-1)
+    //             wave 2: beta of column j-1; wave 3: g(l, j-1) (block 0 only), and for
+    //             P <= 4 also w = T(:, :j-1) g(:, j-1), which is longer than mu there
+    //   [B2, M]   wave 0: mu; wave 1: A_c; wave 2: 1/sigma; wave 3 (P = 8): w
     //   [M, Tb]   wave 0: tau; wave 1: e_c = gamma t_c, f_c = u1 t_c with t_c = A_c + mu B_c;
     //             wave 2: rho_j; wave 3: T(:, j-1) = -beta w
     //   after Tb  every thread: coef_c = tau e_c and the update of its rows below row j.
@@ -396,6 +397,9 @@ __device__ __forceinline__ void panel_run(const PanelArgs &g, int bid)
     // values a wave carries across barriers, by role: wave 0 x1^2 + sigma; wave 1 A_c, B_c;
     // wave 2 1/sigma; wave 3 g, then w
     V<P> cx = zero<P>(), cy = zero<P>();
+    // where w is formed: beside the reduction while the md scalars are cheap (P <= 4); beside mu
+    // for od, whose reduction window is the shorter one in late panels
+    constexpr bool kEarlyW = P <= 4;
     for (int j = 0; j < g.wact; ++j) {
         const long dj = off + j;  // row of the diagonal element of column j
         // ---- 1. one reduction per column: thread (slot, c) sums x_j(i) a_c(i) over its rows i > j:
@@ -440,18 +444,29 @@ __device__ __forceinline__ void panel_run(const PanelArgs &g, int bid)
                 }
                 grid_sync(g.gbar, (nbar + 1) * (unsigned)g.G, g.err);
                 const double *base = g.gpart + (size_t)((nbar & 1) * g.G) * SLOT;
-                ta = acc_zero<P>();
-                for (int i = lane; i < g.G * W; i += 64) {
-                    Acc<P> o;
-                    const double *q = base + (size_t)(i / W) * SLOT + (i % W) * P;
+                // all loads of a batch are issued before the first sum needs them (one round
+                // trip per batch instead of one per term; od, with one term per lane, keeps
+                // its registers); the summation order is unchanged
+                constexpr int NB = (P >= 8) ? 1 : 4;
 #pragma unroll
-                    for (int k = 0; k < P; ++k) o.s[k] = ld_coherent(q + k);
-                    acc_add_acc(ta, o);
+                for (int k = 0; k < P; ++k) hd.x[k] = ld_coherent(base + (W + lane % W) * P + k);
+                ta = acc_zero<P>();
+                const int tot = g.G * W;
+                for (int i0 = lane; i0 < tot; i0 += NB * 64) {
+                    Acc<P> o[NB];
+#pragma unroll
+                    for (int u = 0; u < NB; ++u) {
+                        const int i = i0 + u * 64;
+                        const double *q = base + (size_t)(i / W) * SLOT + (i % W) * P;
+#pragma unroll
+                        for (int k = 0; k < P; ++k) o[u].s[k] = (i < tot) ? ld_coherent(q + k) : 0.0;
+                    }
+#pragma unroll
+                    for (int u = 0; u < NB; ++u)
+                        if (i0 + u * 64 < tot) acc_add_acc(ta, o[u]);
                 }
                 const int lim = (g.G * W < 64) ? g.G * W : 64;
                 for (int m = W; m < lim; m <<= 1) acc_add_acc(ta, shfl_xor_acc(ta, m));
-#pragma unroll
-                for (int k = 0; k < P; ++k) hd.x[k] = ld_coherent(base + (W + lane % W) * P + k);
             }
             const V<P> tot = acc_get(ta);
             // lanes l < W now hold tot = total of column l and hd = a_jl
@@ -465,7 +480,10 @@ __device__ __forceinline__ void panel_run(const PanelArgs &g, int bid)
             }
         } else if (bid == 0 && j > 0) {
             if (wid == 2) t_beta(j - 1);
-            if (wid == 3) cx = t_g(j - 1);
+            if (wid == 3) {
+                cx = t_g(j - 1);
+                if constexpr (kEarlyW) cx = t_w(j - 1, cx);  // in the shadow of the reduction
+            }
         }
         ++nbar;
         __syncthreads();  // B2
@@ -498,7 +516,7 @@ __device__ __forceinline__ void panel_run(const PanelArgs &g, int bid)
         } else if (wid == 2) {
             if (!zs && pos) cx = recip(sig);
         } else if (wid == 3 && bid == 0 && j > 0) {
-            cx = t_w(j - 1, cx);
+            if constexpr (!kEarlyW) cx = t_w(j - 1, cx);
         }
         __syncthreads();  // M
         if (wid == 0) {
