@@ -219,6 +219,86 @@ def precision_run(M, dev, n=2048, tile=128):
     return out
 
 
+def scale_run(M, dev, tile=128):
+    """The other plain-method workloads: the tall 2048 x 1024 least squares in dd/qd/od, and the
+    back substitution at scale (upper-triangular qd, n = 17 920, tile 256, off-diagonals uniform
+    in [-1, 1), diagonal uniform in [1, 2]: the paper's timing input), device-resident and with
+    R, b in and x out over PCIe from pinned host memory (the paper's wall clock)."""
+    import torch
+
+    import mdgen
+    from paper_2110_08375_amd import opcount
+
+    def ev_time(fn, reset, reps=2):
+        out = []
+        for _ in range(reps + 1):
+            reset()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            out.append(e0.elapsed_time(e1))
+        return min(out[1:])
+
+    res = {"tall": {"workload": "least squares m=2048, n=1024, tile 128"}}
+    m, n = 2048, 1024
+    for P in (2, 4, 8):
+        A0, b0 = make_problem(P, m, n, 7100 + P, dev)
+        A, b = torch.empty_like(A0), torch.empty_like(b0)
+        x = torch.empty((P, n), dtype=torch.float64, device=dev)
+        ws = M.workspace(P, m, n, tile, dev)
+        info = torch.zeros(1, dtype=torch.int32, device=dev)
+
+        def reset():
+            A.copy_(A0)
+            b.copy_(b0)
+
+        ms = ev_time(lambda: M.solve(P, A, b, tile, x=x, ws=ws, info=info), reset)
+        tf = opcount.ls_double_ops(P, m, n) / (ms * 1e-3) / 1e12
+        res["tall"][PNAME[P]] = {"ms": round(ms, 3), "tflops": round(tf, 4)}
+        log("tall %s: %.3f ms, %.3f TFLOP/s" % (PNAME[P], ms, tf))
+        del A0, b0, A, b, x, ws
+
+    P, n, tile_bs = 4, 17920, 256
+    R = mdgen.upper_triangular(P, n, 21, device=dev).contiguous()
+    y0 = mdgen.md_vector(P, n, 21, mdgen.STREAM_B, device=dev).contiguous()
+    x = torch.empty_like(y0)
+    ws = M.workspace(P, n, n, tile_bs, dev)
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    ms = ev_time(lambda: M.backsub(P, R, x, tile_bs, ws=ws, info=info), lambda: x.copy_(y0))
+    ops = opcount.backsub_double_ops(P, n)
+    rec = {"workload": "back substitution, upper-triangular qd, n=17920, tile 256", "ms": round(ms, 3),
+           "tflops": round(ops / (ms * 1e-3) / 1e12, 4), "paper_v100_kernel_ms": 237.1,
+           "paper_v100_wall_ms": 2150.0}
+    Rh = torch.empty(R.shape, dtype=torch.float64, pin_memory=True)
+    yh = torch.empty(y0.shape, dtype=torch.float64, pin_memory=True)
+    xh = torch.empty(y0.shape, dtype=torch.float64, pin_memory=True)
+    Rh.copy_(R)
+    yh.copy_(y0)
+    torch.cuda.synchronize()
+    walls = []
+    for _ in range(2):
+        t0 = time.perf_counter()
+        R.copy_(Rh, non_blocking=True)
+        x.copy_(yh, non_blocking=True)
+        M.backsub(P, R, x, tile_bs, ws=ws, info=info)
+        xh.copy_(x, non_blocking=True)
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t0)
+    w = min(walls)
+    rec["wall_ms_incl_pcie"] = round(w * 1e3, 3)
+    rec["wall_tflops_incl_pcie"] = round(ops / w / 1e12, 4)
+    if int(info.item()) != 0:
+        raise RuntimeError("back substitution reported info=%d" % int(info.item()))
+    log("backsub qd n=17920: %.3f ms resident, %.1f ms with transfers" % (ms, w * 1e3))
+    res["backsub_at_scale"] = rec
+    del R, Rh, ws
+    torch.cuda.empty_cache()
+    return res
+
+
 # Paper, Table 5 (V100, complex double double QR of a 512 x 512 matrix): kernel time in ms
 # for the tiles 16 x 32, 8 x 64, 4 x 128 and 2 x 256
 PAPER_TABLE5_COMPLEX_KERNEL_MS = {32: 97.4, 64: 227.4, 128: 238.5, 256: 420.8}
@@ -295,6 +375,8 @@ def main():
     ap.add_argument("--batch", type=int, default=512)
     ap.add_argument("--no-precision", action="store_true", help="skip the refined (precision-form) measurement")
     ap.add_argument("--no-complex", action="store_true", help="skip the complex (Table 5) measurement")
+    ap.add_argument("--no-scale", action="store_true",
+                    help="skip the tall 2048 x 1024 solves and the n = 17920 back substitution")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -499,6 +581,7 @@ def main():
 
     precision = None if args.no_precision else precision_run(M, dev)
     cplx = None if args.no_complex else complex_run(M, dev)
+    scale = None if args.no_scale else scale_run(M, dev)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -532,6 +615,7 @@ def main():
         "batched": batched,
         "precision_form": precision,
         "complex": cplx,
+        "scale": scale,
     }
     print(json.dumps(out), flush=True)
 
