@@ -350,12 +350,22 @@ __device__ __forceinline__ void panel_run(const PanelArgs &g, int bid)
             }
             __syncthreads();
             const double *base = g.gpart + (size_t)((nbar & 1) * g.G) * SLOT;
+            // the workgroups' slots are loaded in batches of NB before they are added (same
+            // order), so a batch costs one round trip
+            constexpr int NB = (P >= 8) ? 1 : 8;
             Acc<P> t = acc_zero<P>();
-            for (int b = psub; b < g.G; b += K) {
-                Acc<P> o;
+            for (int b0 = psub; b0 < g.G; b0 += NB * K) {
+                Acc<P> o[NB];
 #pragma unroll
-                for (int k = 0; k < P; ++k) o.s[k] = ld_coherent(base + (size_t)b * SLOT + pq * P + k);
-                acc_add_acc(t, o);
+                for (int u = 0; u < NB; ++u) {
+                    const int b = b0 + u * K;
+#pragma unroll
+                    for (int k = 0; k < P; ++k)
+                        o[u].s[k] = (b < g.G) ? ld_coherent(base + (size_t)b * SLOT + pq * P + k) : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < NB; ++u)
+                    if (b0 + u * K < g.G) acc_add_acc(t, o[u]);
             }
             pair_sum<P, WW, NT, false>(t, s_comb, s_gram);
         }
