@@ -1440,11 +1440,11 @@ struct Cfg<2> {
 };
 template <>
 struct Cfg<4> {
-    static constexpr int W = 8, NCI = 16;
+    static constexpr int W = 8, NCI = 8;
 };
 template <>
 struct Cfg<8> {
-    static constexpr int W = 4, NCI = 8;
+    static constexpr int W = 4, NCI = 4;
 };
 
 inline int leaf_width(int P)
