@@ -253,13 +253,69 @@ def test_thread_count_independent(orc):
     assert np.array_equal(o1["x"], o4["x"]) and np.array_equal(o1["F"], o4["F"])
 
 
-def test_tally_leading_terms(orc):
-    # md multiplications in QR + Q^T b + back substitution: m n^2 - n^3/3 + O(mn)
-    m, n = 60, 40
-    A = mdgen.md_uniform(2, m, n, 1, mdgen.STREAM_A)
-    out = orc.lstsq(A, mdgen.md_vector(2, m, 1, mdgen.STREAM_B), tally=True)
-    add, mul, div, sq = out["tally"]
-    # sum_j (n-j)(m-j) dot terms plus as many update terms: m n^2 - n^3/3
-    lead = m * n * n - n ** 3 / 3
-    assert abs(mul - lead) / lead < 0.1
-    assert sq == n  # m > n: every column has sigma != 0
+def tally_closed_form(m, n, npos):
+    """Exact md operation counts of the unblocked least-squares solve (Golub-Van Loan 5.1.1 and
+    5.2.1 applied to A and b, then back substitution), as closed-form polynomials in m and n.
+
+    Column j (L = m - j rows from the diagonal) of the QR costs: sigma, L-1 multiplications and
+    additions; mu = sqrt(a_jj^2 + sigma), 1 multiplication, 1 addition, 1 square root; v1,
+    1 addition (x1 <= 0) or 1 addition and 1 division (x1 > 0); beta = 2 v1^2 / (sigma + v1^2),
+    1 multiplication, 1 addition, 1 division; v = x / v1, L-1 divisions; and for each of the
+    n-j-1 columns to its right 2(L-1)+1 multiplications and as many additions.  With m = n the
+    last column has sigma = 0 and stops after its sigma.  Q^T b costs 2L-1 of each per column
+    with beta != 0; back substitution n(n-1)/2 of each and n divisions.  npos is the number of
+    columns with x1 > 0."""
+    sq = n if m > n else n - 1          # columns with sigma != 0
+    s_l1 = n * (m - 1) - n * (n - 1) // 2                        # sum_j (L - 1)
+    s_upd = (2 * (m - n) + 1) * n * (n - 1) // 2 + (n - 1) * n * (2 * n - 1) // 3  # sum_j (n-j-1)(2L-1)
+    s_qtb = 2 * n * m - n * n - (1 if m == n else 0)               # sum_{j: sigma != 0} (2L - 1)
+    tri = n * (n - 1) // 2
+    add = s_l1 + 3 * sq + s_upd + s_qtb + tri
+    mul = s_l1 + 2 * sq + s_upd + s_qtb + tri
+    div = npos + sq + s_l1 + n
+    return add, mul, div, sq
+
+
+def test_closed_form_polynomials_match_their_loop_sums():
+    """The closed forms above against the plain loop sums they summarise (pins the algebra)."""
+    for m, n in ((60, 40), (33, 7), (100, 1), (17, 16), (16, 16), (5, 5), (2, 1)):
+        add = mul = div = sq = 0
+        for j in range(n):
+            L = m - j
+            add += L - 1
+            mul += L - 1
+            if L == 1:  # sigma = 0 (m = n, last column)
+                continue
+            add += 3
+            mul += 2
+            div += 1 + (L - 1)
+            sq += 1
+            add += (n - j - 1) * (2 * L - 1)
+            mul += (n - j - 1) * (2 * L - 1)
+            add += 2 * L - 1  # Q^T b
+            mul += 2 * L - 1
+        add += n * (n - 1) // 2
+        mul += n * (n - 1) // 2
+        div += n
+        assert (add, mul, div, sq) == tally_closed_form(m, n, 0), (m, n)
+
+
+@pytest.mark.parametrize("P,m,n", [(2, 60, 40), (1, 33, 7), (4, 100, 1), (2, 17, 16), (2, 16, 16), (8, 9, 9)])
+def test_tally_exact(orc, P, m, n):
+    """The oracle's operation tally equals the closed-form polynomials exactly, every term.
+    The only data-dependent term is the number of columns with x1 > 0 (one extra division):
+    by Golub-Van Loan 5.1.1, x1 <= 0 gives v1^2 >= sigma and so beta >= 1, x1 > 0 gives
+    v1^2 < sigma and beta < 1, so it is read off the returned betas."""
+    A = mdgen.md_uniform(P, m, n, 11 + m + n, mdgen.STREAM_A)
+    out = orc.lstsq(A, mdgen.md_vector(P, m, 11, mdgen.STREAM_B), tally=True)
+    beta = out["beta"][0]
+    sig_nonzero = n if m > n else n - 1
+    npos = int(np.sum(beta[:sig_nonzero] < 1.0))
+    assert 0 < npos < sig_nonzero or sig_nonzero <= 2
+    assert tuple(out["tally"]) == tally_closed_form(m, n, npos)
+    # the QR alone: the same polynomials without the Q^T b and back-substitution terms
+    F, bt, t = orc.qr(A, tally=True)
+    add, mul, div, sq = tally_closed_form(m, n, npos)
+    s_qtb = 2 * n * m - n * n - (1 if m == n else 0)
+    tri = n * (n - 1) // 2
+    assert tuple(t) == (add - s_qtb - tri, mul - s_qtb - tri, div - n, sq)
