@@ -87,22 +87,26 @@ def measured_fp64():
 
 
 def cpu_baseline(sample, threads):
-    """The CPU oracle (unchanged) on a bounded sample; Table-1 double ops per second."""
+    """The CPU oracle (unchanged) on a bounded sample of square least-squares solves with the
+    benchmark's input recipe; Table-1 double ops per second, blended and per precision."""
     import mdgen
     import oracle
     from paper_2110_08375_amd import opcount
 
     total_ops, total_s = 0.0, 0.0
+    per = {}
     for P, n in sample:
         A, _ = mdgen.ls_problem(P, n, n, 3)
         b = mdgen.md_vector(P, n, 3, mdgen.STREAM_B)
         t0 = time.perf_counter()
         oracle.lstsq(A, b, nthreads=threads)
         dt = time.perf_counter() - t0
+        ops = opcount.ls_double_ops(P, n, n)
         total_s += dt
-        total_ops += opcount.ls_double_ops(P, n, n)
-        log("cpu oracle %s n=%d: %.2f s" % (PNAME[P], n, dt))
-    return total_ops / total_s / 1e12, total_s
+        total_ops += ops
+        per[PNAME[P]] = {"n": n, "s": round(dt, 3), "tflops": ops / dt / 1e12}
+        log("cpu oracle %s n=%d, %d thread(s): %.2f s" % (PNAME[P], n, threads, dt))
+    return total_ops / total_s / 1e12, total_s, per
 
 
 def batched_run(M, P, count, seed, dev, reps, per_problem):
@@ -177,45 +181,62 @@ def batched_run(M, P, count, seed, dev, reps, per_problem):
     return out
 
 
+def fwd_err(x, xt):
+    """max |x - x_true| / max |x_true| of md vectors (limb axis first), the limb differences
+    summed from the bottom (an error estimate, not md arithmetic)"""
+    import numpy as np
+
+    d = np.zeros(xt.shape[1])
+    for k in range(xt.shape[0] - 1, -1, -1):
+        d = d + (x[k] - xt[k])
+    return float(np.max(np.abs(d)) / np.max(np.abs(xt[0])))
+
+
 def precision_run(M, dev, n=2048, tile=128):
     """The precision form: m = n = 2048, kappa = 1e8 (U diag(s) V^T), factor in dd and refine with
-    qd / od residuals, against the plain solver at the target precision (timing only; the
-    accuracy of both is checked in tests/test_gpu_refine.py)."""
-    import numpy as np
+    qd / od residuals until the correction norms show convergence, against the plain solver at
+    the target precision; b = A x_true exact by construction (mdgen.conditioned_exact), so the
+    forward error against x_true is reported for every result."""
     import torch
 
     import mdgen
 
-    A = mdgen.conditioned(2, n, n, 77, kappa=1e8)
-    out = {"workload": "least squares m=n=%d, tile %d, kappa 1e8 (U diag(s) V^T, 8 reflectors each), factor in "
-                       "dd, refine with qd/od residuals, vs the plain solver at qd/od; random right-hand side "
-                       "(timing only)" % (n, tile)}
-    Ag = torch.from_numpy(A).to(dev)
-    for P, iters in ((4, 4), (8, 6)):
-        b = torch.from_numpy(mdgen.md_vector(P, n, 78, mdgen.STREAM_B)).to(dev)
+    out = {"workload": "least squares m=n=%d, tile %d, kappa 1e8 (U diag(s) V^T, 8 reflectors each, entries on a "
+                       "2^-50 grid), b = A x_true exact; factor in dd, refine with qd/od residuals until the "
+                       "correction norms converge, vs the plain solver at qd/od; forward error vs x_true" % (n, tile)}
+    for P, iters in ((4, 8), (8, 10)):
+        A, xt, b = mdgen.conditioned_exact(P, n, n, 77, kappa=1e8)
+        Ag = torch.from_numpy(A[:2].copy()).to(dev)
+        bg = torch.from_numpy(b).to(dev)
         ws = M.refined_workspace(P, n, n, tile, dev)
         F = torch.empty_like(Ag)
         ms = []
         for _ in range(2):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record()
-            M.solve_refined(P, Ag, b, tile, iters, F=F, ws=ws)
+            x, info, norms = M.solve_refined(P, Ag, bg, tile, iters, F=F, ws=ws)
             e1.record()
             torch.cuda.synchronize()
             ms.append(e0.elapsed_time(e1))
-        Ap = torch.zeros((P, n, n), dtype=torch.float64, device=dev)
-        Ap[:2] = Ag
-        bp = b.clone()
+        steps = int((norms.cpu().numpy().reshape(-1, 2)[:, 0] >= 0).sum())
+        err_r = fwd_err(x.cpu().numpy(), xt)
+        Ap = torch.from_numpy(A).to(dev)
+        bp = bg.clone()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        M.solve(P, Ap, bp, tile)
+        xp, infop = M.solve(P, Ap, bp, tile)
         e1.record()
         torch.cuda.synchronize()
         mp = e0.elapsed_time(e1)
-        out[PNAME[P]] = {"refined_ms": round(ms[-1], 3), "iters": iters, "plain_ms": round(mp, 3),
+        err_p = fwd_err(xp.cpu().numpy(), xt)
+        if int(info.item()) != 0 or int(infop.item()) != 0:
+            raise RuntimeError("precision form: info %d / %d" % (int(info.item()), int(infop.item())))
+        out[PNAME[P]] = {"refined_ms": round(ms[-1], 3), "steps": steps, "max_steps": iters,
+                         "refined_fwd_err": err_r, "plain_ms": round(mp, 3), "plain_fwd_err": err_p,
                          "speedup": round(mp / ms[-1], 2)}
-        log("precision form %s: refined %.2f ms, plain %.2f ms" % (PNAME[P], ms[-1], mp))
-        del Ap, bp, F, ws
+        log("precision form %s: refined %.2f ms (%d steps, err %.2e), plain %.2f ms (err %.2e)"
+            % (PNAME[P], ms[-1], steps, err_r, mp, err_p))
+        del Ap, bp, F, ws, Ag, bg
     return out
 
 
@@ -391,6 +412,8 @@ def main():
 
     M.lib()
     dev = torch.device("cuda:0")
+    torch.zeros(1, device=dev)
+    M.init()  # the look-ahead side stream of this thread
     m, n, tile = args.m, args.n, args.tile
     precs = [int(p) for p in args.precisions.split(",")]
     log("device %s, m=%d n=%d tile=%d precisions=%s" % (torch.cuda.get_device_name(0), m, n, tile, precs))
@@ -585,12 +608,20 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        # all host cores the process may use (the box sets OMP_NUM_THREADS), and one thread
+        threads = int(os.environ.get("OMP_NUM_THREADS", 0)) or len(os.sched_getaffinity(0))
         sample = [(2, 1024), (4, 512), (8, 256)]
-        v, secs = cpu_baseline(sample, threads)
+        v, secs, per = cpu_baseline(sample, threads)
+        sample1 = [(2, 256), (4, 128), (8, 128)]
+        v1, secs1, per1 = cpu_baseline(sample1, 1)
         cpu = {"value": v, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
                "sample": "oracle least squares (unblocked Householder QR + Q^T b + back substitution) on square "
-                         "dd n=1024, qd n=512, od n=256 with the same input recipe; %.1f s" % secs}
+                         "dd n=1024, qd n=512, od n=256 with the same input recipe, %d threads; %.1f s"
+                         % (threads, secs),
+               "nproc": os.cpu_count(), "per_precision": per,
+               "single_thread": {"value": v1, "cores": 1, "per_precision": per1,
+                                 "sample": "the same solve on square dd n=256, qd n=128, od n=128, one "
+                                           "thread; %.1f s" % secs1}}
 
     out = {
         "metric": METRIC,

@@ -11,21 +11,33 @@
  * Storage (the paper's staging, end of Section 2): a matrix of multiple doubles is P planes
  * of doubles, most significant limb first.  Plane k starts ld * cols doubles after plane
  * k - 1 and is column-major with leading dimension ld >= rows.  A vector of length L is P
- * planes of L doubles.  Every pointer below is a DEVICE pointer.  The caller owns every
- * buffer; the library never allocates device memory or frees, and synchronises only in the
- * set-up and tuning calls that say so (mdls_batch_plan, mdls_batch_autotune).  Work is enqueued
- * on the caller's stream; the QR additionally forks part of each trailing update onto a
- * side stream owned by the calling host thread (created once per device on first use, default
- * priority) and joins it back with events before returning, so the caller's stream orders
- * everything and a call sequence can still be captured into a HIP graph (the first call on a
- * thread should happen outside capture).  MDLS_LOOKAHEAD=0 keeps all work on the caller's
- * stream.
+ * planes of L doubles.  Every pointer below is a DEVICE pointer unless it says HOST.  The
+ * caller owns every buffer; the library never allocates device memory or frees, and
+ * synchronises only in the set-up and tuning calls that say so (mdls_init, mdls_finalize,
+ * mdls_batch_plan, mdls_batch_autotune).  Work is enqueued on the caller's stream.  After
+ * mdls_init on the calling host thread, the QR also forks part of each trailing update onto a
+ * side stream that mdls_init created for that thread and device (default priority), and joins
+ * it back with events before returning; the caller's stream still orders everything, and a
+ * call can be captured into a HIP graph.  Without mdls_init every kernel runs on the caller's
+ * stream (same results, bit for bit).  No solve call creates a stream or an event.
  *
  * Errors: a call returns 0 on success; -i when argument i (1-based) is invalid, checked on
- * the host before anything is enqueued (LAPACK convention); MDLS_EHIP when a launch fails.
+ * the host before anything is enqueued (LAPACK convention); MDLS_EHIP when a launch fails;
+ * MDLS_EUNSUPPORTED for valid arguments the library does not handle (too many rows for the
+ * panel kernel, or a device with too few compute units for its workgroups).
  * Numerical status is written asynchronously to the device int *d_info where a call has
- * one: 0 = success, k > 0 = R(k,k) is exactly zero (1-based), x then unspecified.
- * NaN and Inf in the input propagate to the output unchecked.  No call throws.
+ * one: 0 = success, k > 0 = R(k,k) is exactly zero (1-based), x then unspecified; -1 = a
+ * grid barrier of the factorisation gave up waiting (see below), the results are unspecified.
+ * NaN and Inf in the input propagate to the output unchecked (d_info stays 0 unless R(k,k) is
+ * exactly zero).  No call throws.
+ *
+ * Co-residency: a Householder panel of more than one workgroup synchronises its workgroups
+ * once per column with a grid barrier, so all of them must be resident at once.  The library
+ * checks that the panel's workgroups fit the device (occupancy x compute units) and otherwise
+ * returns MDLS_EUNSUPPORTED; the concurrent trailing update never waits, so it cannot block
+ * them.  Work of other processes or streams that holds compute units for longer than the
+ * barrier's spin limit (about 0.1 s by default) can still make a barrier give up: it then
+ * lets its workgroup continue, every kernel exits normally, and *d_info reports -1.
  *
  * Threading: calls on distinct streams with distinct buffers and workspaces may run
  * concurrently.  One workspace must not be used by two calls in flight at once.
@@ -47,6 +59,43 @@ typedef enum { MDLS_F64 = 1, MDLS_DD = 2, MDLS_QD = 4, MDLS_OD = 8 } mdls_prec;
 #define MDLS_EHIP (-100)        /* a kernel launch failed */
 #define MDLS_EUNSUPPORTED (-101) /* valid arguments outside what the library handles */
 
+/*
+ * Set-up of the calling host thread on the current device: creates the look-ahead side stream
+ * and its events, and queries the panel kernels' occupancy.  Call it before the first solve
+ * (and before any graph capture) on each thread that wants the concurrent trailing update;
+ * repeated calls do nothing.  mdls_finalize waits for the side stream and destroys it (the
+ * thread's later calls then run on the caller's stream alone).  Both return 0 or MDLS_EHIP
+ * (MDLS_EUNSUPPORTED for a device index above 15).
+ */
+int mdls_init(void);
+int mdls_finalize(void);
+
+/*
+ * Process-wide tuning, for benchmarks and tests; the defaults are built in and nothing is
+ * read from the environment.  Only MDLS_TUNE_PANEL_VARIANT changes results (it changes the
+ * panel's workgroup shape and so its reduction order); the others change only speed or, for
+ * the spin limit, how long a grid barrier waits before it reports -1 through *d_info.
+ *   MDLS_TUNE_LOOKAHEAD        1 (default): concurrent trailing update after mdls_init; 0: off
+ *   MDLS_TUNE_PANEL_VARIANT    0 (default) or 1: the panel kernel's alternative shape (more rows
+ *                              per thread: dd 512 x 8, qd 256 x 4, od 256 x 2 threads x rows)
+ *   MDLS_TUNE_APPLY_GRID_CAP   workgroups of the concurrent trailing update; 0 (default): 448
+ *                              (two per CU on 224 CUs), for od 224 once fewer than
+ *                              MDLS_TUNE_APPLY_WIDE_ROWS (default 768) rows remain
+ *   MDLS_TUNE_SPIN_LIMIT       polls (each after a sleep of about 64 cycles) before a grid
+ *                              barrier gives up; default 2^22
+ * mdls_set_tuning returns 0, -1 for an unknown option, -2 for a value out of range;
+ * mdls_get_tuning returns the current value (-1 for an unknown option).
+ */
+enum {
+    MDLS_TUNE_LOOKAHEAD = 1,
+    MDLS_TUNE_PANEL_VARIANT = 2,
+    MDLS_TUNE_APPLY_GRID_CAP = 3,
+    MDLS_TUNE_APPLY_WIDE_ROWS = 4,
+    MDLS_TUNE_SPIN_LIMIT = 5
+};
+int mdls_set_tuning(int option, long value);
+long mdls_get_tuning(int option);
+
 /* Largest number of rows the Householder panel kernel holds on chip, for precision p. */
 int mdls_max_rows(int p);
 
@@ -57,26 +106,34 @@ int mdls_max_rows(int p);
 size_t mdls_workspace_bytes(int p, int m, int n, int tile);
 
 /*
- * Householder QR (paper Algorithm 2).  A (m x n, lda >= m) is overwritten: R in the upper
- * triangle, the Householder vector v_j of column j below the diagonal (v_j has a unit
- * first entry that is not stored; v_j and beta_j as in Golub-Van Loan Algorithm 5.1.1, so
- * R(j,j) >= 0 whenever the column below the diagonal is not exactly zero, and beta_j = 0
- * with R(j,j) unchanged when it is).
+ * Householder QR (paper Section 3, Algorithm 2: inputs A, tile size and tile count; outputs R
+ * and the blocked reflectors; the Householder vector and beta of each column as the paper
+ * takes them from Golub and Van Loan, Algorithm 5.1.1).  A (m x n, lda >= m) is overwritten:
+ * R in the upper triangle, the Householder vector v_j of column j below the diagonal (unit
+ * first entry not stored), so R(j,j) >= 0 whenever the column below the diagonal is not
+ * exactly zero, and beta_j = 0 with R(j,j) unchanged when it is.
+ * beta (may be NULL): P planes of n, receives beta_0 .. beta_{n-1}.
  * T (may be NULL): P planes of ldt x n, ldt >= tile.  For each tile block k (columns
  * k*tile .. k*tile+tile-1) rows 0..tile-1 of those columns receive the upper-triangular
  * tile x tile factor T_k with H_{k*tile} ... H_{k*tile+tile-1} = I - Y_k T_k Y_k^T, Y_k the
- * unit lower trapezoidal block of Householder vectors; diag(T_k) holds the beta_j.  The
- * paper's W of P_WY = I + W Y^T is W_k = -Y_k T_k (see mdls_form_w).
- * Requires n % tile == 0 when T != NULL, and m <= mdls_max_rows(p).
+ * unit lower trapezoidal block of Householder vectors; diag(T_k) holds the beta_j.
+ * Deviation from the paper's output list: Algorithm 2 returns the W of P_WY = I + W Y^T
+ * (Section 3, the recurrence for the columns of W) and the explicit Q; this call returns the
+ * compact factor T instead, from which W_k = -Y_k T_k on request (mdls_form_w) and Q on
+ * request (mdls_form_q), because Q^T b needs only Y and T (identical in exact arithmetic).
+ * d_info (may be NULL): 0, or -1 if a grid barrier gave up (see the top of this file).
+ * Requires n % tile == 0 when T != NULL, and m <= mdls_max_rows(p).  Status -1..-11 for
+ * arguments 1..11.
  */
-int mdls_qr(int p, int m, int n, int tile, double *A, int lda, double *T, int ldt, void *ws,
-            size_t ws_bytes, hipStream_t stream);
+int mdls_qr(int p, int m, int n, int tile, double *A, int lda, double *beta, double *T, int ldt,
+            void *ws, size_t ws_bytes, int *d_info, hipStream_t stream);
 
 /*
- * B := Q^T B with Q = H_0 H_1 ... H_{n-1} from mdls_qr (paper Section 1: A x = b becomes
- * R x = Q^T b).  A and T as returned by mdls_qr with the same tile.  B is m x nrhs
- * (ldb >= m).  Applies the tile blocks in order: B := (I - Y_k T_k^T Y_k^T) B, which is
- * the paper's B + Y_k (W_k^T B).
+ * B := Q^T B with Q = H_0 H_1 ... H_{n-1} from mdls_qr (paper Section 1: with A = QR the
+ * system A x = b becomes R x = Q^T b; Section 3, the update with the blocked reflector).
+ * A and T as returned by mdls_qr with the same tile.  B is m x nrhs (ldb >= m).  Applies the
+ * tile blocks in order: B := (I - Y_k T_k^T Y_k^T) B, which is the paper's B + Y_k (W_k^T B)
+ * with W_k = -Y_k T_k; it takes T where the paper's interface would take W (see mdls_qr).
  */
 int mdls_apply_qt(int p, int m, int n, int tile, const double *A, int lda, const double *T,
                   int ldt, double *B, int ldb, int nrhs, void *ws, size_t ws_bytes,
@@ -105,19 +162,25 @@ int mdls_form_w(int p, int m, int n, int tile, const double *A, int lda, const d
                 int ldt, double *W, int ldw, hipStream_t stream);
 
 /*
- * Tiled back substitution (paper Algorithm 1): solves R x = y with R the upper triangle of
+ * Tiled back substitution (paper Section 2, Algorithm 1: input the N x N tiles of an upper
+ * triangular U and b; output x with U x = b): solves R x = y with R the upper triangle of
  * the leading n x n block of R (ldr >= n, entries below the diagonal are not read), n a
  * multiple of tile.  x holds y on entry (P planes of n doubles) and the solution on exit.
  * Stage 1 inverts the n/tile diagonal tiles, stage 2 alternates x_i := U_i^{-1} b_i with
- * b_j -= A_{j,i} x_i for j < i.  *d_info as described above.
+ * b_j -= A_{j,i} x_i for j < i.  *d_info: 0, or k > 0 for the first exactly zero R(k,k).
  */
 int mdls_backsub(int p, int n, int tile, const double *R, int ldr, double *x, void *ws,
                  size_t ws_bytes, int *d_info, hipStream_t stream);
 
 /*
- * Least squares: A (m x n) and b (P planes of m) are overwritten by the factors and by
- * Q^T b; x (P planes of n) receives the solution of R x = (Q^T b)(0:n).  tile is the back
- * substitution tile (n % tile == 0).  *d_info as above.
+ * Least squares (paper Section 1: the solution of A x = b in the least-squares sense via
+ * A = QR and R x = Q^T b; Section 4, the least-squares runs time QR and back substitution
+ * together): Algorithm 2 with Q^T b carried as an extra column of every trailing update, then
+ * Algorithm 1 on R x = (Q^T b)(0:n).  A (m x n) and b (P planes of m) are overwritten by the
+ * factors (as mdls_qr, without T) and by Q^T b, whose rows n..m-1 hold the residual's
+ * coordinates; x (P planes of n) receives the solution.  tile is the back substitution tile
+ * (n % tile == 0).  *d_info: 0; k > 0 for the first exactly zero R(k,k); -1 if a grid barrier
+ * gave up.  Status -1..-11 for arguments 1..11.
  */
 int mdls_solve(int p, int m, int n, int tile, double *A, int lda, double *b, double *x,
                void *ws, size_t ws_bytes, int *d_info, hipStream_t stream);
@@ -250,9 +313,15 @@ typedef struct {
  * p_out limbs (x = 0 in the first), d := R^-1 (Q^T r)(0:n) in dd (r rounded to dd; Q^T by the
  * tile reflectors, R^-1 by the tiled back substitution of Section 2), x += d in p_out limbs.
  * b: P = p_out planes of m; x: p_out planes of n (output).  Each step gains about
- * -log10(kappa(A) 2^-105) digits while kappa(A) 2^-105 << 1 and b is consistent (b = A x*);
- * d_norms (2 iters device doubles) receives max |d| and max |x| (leading limbs) of each step,
- * so the caller can see the convergence.  *d_info as for mdls_solve.  n % tile == 0.
+ * -log10(kappa(A) 2^-105) digits while kappa(A) 2^-105 << 1 (for an inconsistent b the
+ * contraction also grows with kappa(A)^2 times the relative residual).  iters is the most
+ * steps taken: the call stops on the device once the correction norms show convergence, when
+ * max|d| <= u max|x| or when the next correction estimated from the observed contraction,
+ * d_k^2 / d_(k-1), is below u max|x| (u = 2^-(53 p_out - p_out + 1)); later steps' kernels then
+ * return at once, so the call stays asynchronous and capturable.  The tile inverses of R are
+ * formed once.  d_norms (2 iters device doubles) receives max |d| and max |x| (leading limbs)
+ * of each step taken and -1, -1 for steps not taken.  *d_info as for mdls_solve.
+ * n % tile == 0.
  *   mdls_refined_workspace_bytes(p_out, m, n, tile)   workspace (0 if arguments invalid).
  */
 size_t mdls_refined_workspace_bytes(int p_out, int m, int n, int tile);

@@ -268,6 +268,40 @@ def conditioned(P: int, m: int, n: int, seed: int, kappa: float = 1e8, reflector
     return md_from_leading(np.ascontiguousarray(M.T), P, seed, STREAM_A, 0)
 
 
+def conditioned_exact(P: int, m: int, n: int, seed: int, kappa: float = 1e8, reflectors: int = 8):
+    """The precision-form matrix with a right-hand side that is exact by construction.
+
+    A is the leading limb of ``conditioned`` rounded to a multiple of 2**-50 (a change below
+    2**-51 per entry, which moves the singular values by less than 2**-51 sqrt(m n), far below
+    1/kappa for the sizes used), stored as one nonzero limb of P; x_true has entries that are
+    multiples of 1/16 in [-1, 1]; b = A x_true is formed in exact integer arithmetic (every
+    product is an integer multiple of 2**-54) and split into its two leading doubles, which
+    represent it exactly.  Returns A (P, n, m), x_true (P, n), b (P, m), all numpy."""
+    A0 = conditioned(1, m, n, seed, kappa, reflectors)[0]          # (n, m) = [col, row]
+    ia = np.round(A0 * 2.0 ** 50).astype(np.int64)                  # |A| <= 1, so |ia| <= 2**50
+    ix = np.round(uniform(seed, STREAM_X, n) * 16.0).astype(np.int64)  # |ix| <= 16
+    # sum_j ia_ij ix_j with ia = hi 2**25 + lo: two int64 products (|.| < 2**44 each), then Python ints
+    hi = ia >> 25
+    lo = ia - (hi << 25)
+    s_hi = hi.T @ ix
+    s_lo = lo.T @ ix
+    A = np.zeros((P, n, m), dtype=np.float64)
+    A[0] = ia.astype(np.float64) * 2.0 ** -50
+    x = np.zeros((P, n), dtype=np.float64)
+    x[0] = ix.astype(np.float64) / 16.0
+    b = np.zeros((P, m), dtype=np.float64)
+    for i in range(m):
+        S = (int(s_hi[i]) << 25) + int(s_lo[i])                     # b_i = S 2**-54 exactly
+        h = float(S)
+        r = S - int(h)
+        lo_d = float(r)
+        assert r - int(lo_d) == 0, "b_i does not fit two doubles"
+        b[0, i] = math.ldexp(h, -54)
+        if P > 1:
+            b[1, i] = math.ldexp(lo_d, -54)
+    return A, x, b
+
+
 def ls_problem(P: int, m: int, n: int, seed: int, ones_solution: bool = False, device=None):
     """A (P, n, m) and x_true (P, n) for a least-squares test problem."""
     A = md_uniform(P, m, n, seed, STREAM_A, device=device)

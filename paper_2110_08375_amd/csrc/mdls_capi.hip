@@ -2,6 +2,7 @@
 // per-precision drivers (instantiated in mdls_p1/2/4/8.hip).
 #include <algorithm>
 #include <cstring>
+#include <atomic>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -55,52 +56,80 @@ hipEvent_t pool_get()
 namespace mdls_impl {
 bool timing_on() { return g_on; }
 
+// Side streams: one per (host thread, device), created by mdls_init and destroyed by
+// mdls_finalize; a solve never creates one.
+namespace {
+constexpr int kMaxDev = 16;
+struct PerThread {
+    SideStream ss{};
+    bool ok = false;
+};
+thread_local PerThread t_side[kMaxDev];
+
+std::atomic<int> g_lookahead{1};
+std::atomic<int> g_panel_variant{0};
+std::atomic<int> g_apply_grid_cap{0};
+std::atomic<int> g_apply_wide_rows{768};
+std::atomic<unsigned> g_spin_limit{1u << 22};
+
+// occupancy-derived capacity of the panel kernel, per (device, precision index, variant)
+std::atomic<int> g_capacity[kMaxDev][4][2];
+
+int pidx(int P) { return P == 1 ? 0 : P == 2 ? 1 : P == 4 ? 2 : 3; }
+
+}  // namespace
+
 SideStream *side_stream()
 {
-    struct PerThread {
-        int dev = -1;
-        SideStream ss{};
-        bool ok = false;
-    };
-    static thread_local PerThread slots[16];
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 16) return nullptr;
-    PerThread &p = slots[dev];
-    if (!p.ok) {
-        if (hipStreamCreateWithFlags(&p.ss.q, hipStreamNonBlocking) != hipSuccess) return nullptr;
-        if (hipEventCreateWithFlags(&p.ss.ev_panel, hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&p.ss.ev_wide[0], hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&p.ss.ev_wide[1], hipEventDisableTiming) != hipSuccess)
-            return nullptr;
-        p.dev = dev;
-        p.ok = true;
-    }
-    return &p.ss;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDev) return nullptr;
+    return t_side[dev].ok ? &t_side[dev].ss : nullptr;
 }
 
-bool lookahead_on()
+Tuning tuning()
 {
-    const char *e = getenv("MDLS_LOOKAHEAD");
-    return !(e && e[0] == '0');
+    Tuning t;
+    t.lookahead = g_lookahead.load(std::memory_order_relaxed);
+    t.panel_variant = g_panel_variant.load(std::memory_order_relaxed);
+    t.apply_grid_cap = g_apply_grid_cap.load(std::memory_order_relaxed);
+    t.apply_wide_rows = g_apply_wide_rows.load(std::memory_order_relaxed);
+    t.spin_limit = g_spin_limit.load(std::memory_order_relaxed);
+    return t;
 }
 
 // Workgroups of a concurrent trailing update of h rows (grid-stride beyond): two per CU for dd
 // and qd, whose panels have slack; for od, whose panel and update are balanced, two per CU only
-// while the update is much longer than the panel (measured on the n = 1024 solves).
-// MDLS_APPLY_GRID_CAP overrides.
+// while the update is much longer than the panel (h >= apply_wide_rows), then one per CU on 224
+// CUs (measured on the n = 1024 solves).
 int apply_grid_cap(int P, int h)
 {
-    const char *e = getenv("MDLS_APPLY_GRID_CAP");
-    if (e) {
-        const int v = atoi(e);
-        if (v > 0) return v;
-    }
+    const Tuning t = tuning();
+    if (t.apply_grid_cap > 0) return t.apply_grid_cap;
     if (P < 8) return 448;
-    // od: two per CU too while the update is much longer than the panel (h >= 768 rows), then
-    // one per CU on 224 CUs
-    const char *w = getenv("MDLS_APPLY_WIDE_ROWS");
-    const int wide = w ? atoi(w) : 768;
-    return h >= wide ? 448 : 224;
+    return h >= t.apply_wide_rows ? 448 : 224;
+}
+
+int panel_capacity(int P)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDev) return 0;
+    const int v = tuning().panel_variant ? 1 : 0;
+    std::atomic<int> &slot = g_capacity[dev][pidx(P)][v];
+    int c = slot.load(std::memory_order_relaxed);
+    if (c > 0) return c;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) return 0;
+    const PanelCfg cf = panel_cfg(P, v);
+    int per_cu = 0;
+    switch (P) {
+    case 1: per_cu = panel_occupancy_t<1>(cf); break;
+    case 2: per_cu = panel_occupancy_t<2>(cf); break;
+    case 4: per_cu = panel_occupancy_t<4>(cf); break;
+    default: per_cu = panel_occupancy_t<8>(cf); break;
+    }
+    c = per_cu * cus;
+    if (c > 0) slot.store(c, std::memory_order_relaxed);
+    return c;
 }
 
 void timing_begin(hipStream_t s, void **ev)
@@ -225,8 +254,8 @@ size_t mdls_workspace_bytes(int p, int m, int n, int tile)
     return layout(p, m, n, tile).total;
 }
 
-int mdls_qr(int p, int m, int n, int tile, double *A, int lda, double *T, int ldt, void *ws, size_t ws_bytes,
-            hipStream_t stream)
+int mdls_qr(int p, int m, int n, int tile, double *A, int lda, double *beta, double *T, int ldt, void *ws,
+            size_t ws_bytes, int *d_info, hipStream_t stream)
 {
     if (!valid_p(p)) return -1;
     if (m < 1) return -2;
@@ -234,11 +263,11 @@ int mdls_qr(int p, int m, int n, int tile, double *A, int lda, double *T, int ld
     if (!valid_tile(tile) || (T && n % tile != 0)) return -4;
     if (!A) return -5;
     if (lda < m) return -6;
-    if (T && ldt < tile) return -8;
-    if (!ws) return -9;
-    if (ws_bytes < mdls_workspace_bytes(p, m, n, tile)) return -10;
-    if (m > mdls_max_rows(p)) return MDLS_EUNSUPPORTED;
-    return dispatch<QrF>(p, m, n, tile, A, lda, T, ldt, ws, stream);
+    if (T && ldt < tile) return -9;
+    if (!ws) return -10;
+    if (ws_bytes < mdls_workspace_bytes(p, m, n, tile)) return -11;
+    if (m > mdls_max_rows(p) || panel_groups(p, m) > panel_capacity(p)) return MDLS_EUNSUPPORTED;
+    return dispatch<QrF>(p, m, n, tile, A, lda, beta, T, ldt, ws, d_info, stream);
 }
 
 int mdls_apply_qt(int p, int m, int n, int tile, const double *A, int lda, const double *T, int ldt, double *B,
@@ -481,7 +510,7 @@ int mdls_solve(int p, int m, int n, int tile, double *A, int lda, double *b, dou
     if (!ws) return -9;
     if (ws_bytes < mdls_workspace_bytes(p, m, n, tile)) return -10;
     if (!d_info) return -11;
-    if (m > mdls_max_rows(p)) return MDLS_EUNSUPPORTED;
+    if (m > mdls_max_rows(p) || panel_groups(p, m) > panel_capacity(p)) return MDLS_EUNSUPPORTED;
     return dispatch<SolveF>(p, m, n, tile, A, lda, b, x, ws, d_info, stream);
 }
 
@@ -615,9 +644,83 @@ int mdls_solve_refined(int p_out, int m, int n, int tile, const double *A, int l
     if (ws_bytes < mdls_refined_workspace_bytes(p_out, m, n, tile)) return -12;
     if (!d_info) return -13;
     if (!d_norms) return -14;
-    if (m > mdls_max_rows(2)) return MDLS_EUNSUPPORTED;
+    if (m > mdls_max_rows(2) || panel_groups(2, m) > panel_capacity(2)) return MDLS_EUNSUPPORTED;
     if (p_out == 4) return refine_t<4>(m, n, tile, A, lda, b, x, iters, F, ws, d_info, d_norms, stream);
     return refine_t<8>(m, n, tile, A, lda, b, x, iters, F, ws, d_info, d_norms, stream);
+}
+
+int mdls_init(void)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return MDLS_EHIP;
+    if (dev < 0 || dev >= kMaxDev) return MDLS_EUNSUPPORTED;
+    PerThread &p = t_side[dev];
+    if (p.ok) return 0;
+    if (hipStreamCreateWithFlags(&p.ss.q, hipStreamNonBlocking) != hipSuccess) return MDLS_EHIP;
+    if (hipEventCreateWithFlags(&p.ss.ev_panel, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&p.ss.ev_wide[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&p.ss.ev_wide[1], hipEventDisableTiming) != hipSuccess)
+        return MDLS_EHIP;
+    for (int P : {1, 2, 4, 8})
+        if (panel_capacity(P) < 1) return MDLS_EHIP;
+    p.ok = true;
+    return 0;
+}
+
+int mdls_finalize(void)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return MDLS_EHIP;
+    if (dev < 0 || dev >= kMaxDev) return MDLS_EUNSUPPORTED;
+    PerThread &p = t_side[dev];
+    if (!p.ok) return 0;
+    p.ok = false;
+    int rc = 0;
+    if (hipStreamSynchronize(p.ss.q) != hipSuccess) rc = MDLS_EHIP;
+    if (hipEventDestroy(p.ss.ev_panel) != hipSuccess || hipEventDestroy(p.ss.ev_wide[0]) != hipSuccess ||
+        hipEventDestroy(p.ss.ev_wide[1]) != hipSuccess || hipStreamDestroy(p.ss.q) != hipSuccess)
+        rc = MDLS_EHIP;
+    return rc;
+}
+
+int mdls_set_tuning(int option, long value)
+{
+    switch (option) {
+    case MDLS_TUNE_LOOKAHEAD:
+        if (value != 0 && value != 1) return -2;
+        g_lookahead.store((int)value);
+        return 0;
+    case MDLS_TUNE_PANEL_VARIANT:
+        if (value != 0 && value != 1) return -2;
+        g_panel_variant.store((int)value);
+        return 0;
+    case MDLS_TUNE_APPLY_GRID_CAP:
+        if (value < 0 || value > 65536) return -2;
+        g_apply_grid_cap.store((int)value);
+        return 0;
+    case MDLS_TUNE_APPLY_WIDE_ROWS:
+        if (value < 0 || value > (1L << 30)) return -2;
+        g_apply_wide_rows.store((int)value);
+        return 0;
+    case MDLS_TUNE_SPIN_LIMIT:
+        if (value < 0 || value > (1L << 30)) return -2;
+        g_spin_limit.store((unsigned)value);
+        return 0;
+    }
+    return -1;
+}
+
+long mdls_get_tuning(int option)
+{
+    const Tuning t = tuning();
+    switch (option) {
+    case MDLS_TUNE_LOOKAHEAD: return t.lookahead;
+    case MDLS_TUNE_PANEL_VARIANT: return t.panel_variant;
+    case MDLS_TUNE_APPLY_GRID_CAP: return t.apply_grid_cap;
+    case MDLS_TUNE_APPLY_WIDE_ROWS: return t.apply_wide_rows;
+    case MDLS_TUNE_SPIN_LIMIT: return (long)t.spin_limit;
+    }
+    return -1;
 }
 
 int mdls_timing_enable(int on)

@@ -51,6 +51,7 @@ struct PanelArgs {
     unsigned *gbar; // barrier counter of this launch, zero on entry
     int *err;       // set to 1 if a barrier times out
     int G;          // workgroups in the launch
+    unsigned spin;  // polls before a barrier gives up
 };
 
 // Entry (r, c) of a block of Householder vectors stored below the diagonal of A: zero above
@@ -64,9 +65,9 @@ __device__ __forceinline__ V<P> y_entry(const double *Y, long ldy, long psy, lon
 }
 
 // All workgroups of the launch meet here (called by one whole wave per workgroup).  The
-// spin is bounded: a timed-out barrier raises *err and lets the wave continue, so the grid
-// always drains.
-__device__ inline void grid_sync(unsigned *ctr, unsigned target, int *err)
+// spin is bounded (spin polls, each after a short sleep): a timed-out barrier raises *err and
+// lets the wave continue, so the grid always drains; the host turns *err into a status.
+__device__ inline void grid_sync(unsigned *ctr, unsigned target, int *err, unsigned spin)
 {
     const int lane = threadIdx.x & 63;
     // the fence before the relaxed arrival releases this workgroup's stores; the relaxed
@@ -77,7 +78,7 @@ __device__ inline void grid_sync(unsigned *ctr, unsigned target, int *err)
         unsigned spins = 0;
         while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             __builtin_amdgcn_s_sleep(1);
-            if (++spins > (1u << 22)) {
+            if (++spins > spin) {
                 __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 break;
             }
@@ -346,7 +347,7 @@ __device__ __forceinline__ void panel_run(const PanelArgs &g, int bid)
 #pragma unroll
                     for (int k = 0; k < P; ++k) st_coherent(mine + q * P + k, s_gram[q * P + k]);
                 }
-                grid_sync(g.gbar, (nbar + 1) * (unsigned)g.G, g.err);
+                grid_sync(g.gbar, (nbar + 1) * (unsigned)g.G, g.err, g.spin);
             }
             __syncthreads();
             const double *base = g.gpart + (size_t)((nbar & 1) * g.G) * SLOT;
@@ -452,7 +453,7 @@ __device__ __forceinline__ void panel_run(const PanelArgs &g, int bid)
                         for (int k = 0; k < P; ++k) st_coherent(mine + (W + lane) * P + k, hd.x[k]);
                     }
                 }
-                grid_sync(g.gbar, (nbar + 1) * (unsigned)g.G, g.err);
+                grid_sync(g.gbar, (nbar + 1) * (unsigned)g.G, g.err, g.spin);
                 const double *base = g.gpart + (size_t)((nbar & 1) * g.G) * SLOT;
                 // all loads of a batch are issued before the first sum needs them (one round
                 // trip per batch instead of one per term; od, with one term per lane, keeps
@@ -863,6 +864,7 @@ struct BatchArgs {
     unsigned *tctr;     // per problem: kTeamCtrs barrier counters, zero on entry
     double *xch;        // per problem: T (W^2 P) and panel_run's exchange slots (2 kTeamMax (W^2 + 2W) P)
     int *err;           // set if a team barrier times out
+    unsigned spin;      // polls before a team barrier gives up
     int *info;          // per problem
     long long *times;   // per problem: start, end; or null
 };
@@ -989,7 +991,7 @@ __global__ __launch_bounds__(NT) void k_batch(BatchArgs g)
             if (team > 1) {
                 __syncthreads();
                 ++nsync;
-                if (wid == 0) grid_sync(ctr, nsync * (unsigned)team, g.err);
+                if (wid == 0) grid_sync(ctr, nsync * (unsigned)team, g.err, g.spin);
                 __syncthreads();
             }
         };
@@ -1015,6 +1017,7 @@ __global__ __launch_bounds__(NT) void k_batch(BatchArgs g)
             pa.gbar = ctr + 1 + c0 / W;
             pa.err = g.err;
             pa.G = team;
+            pa.spin = g.spin;
             panel_run<P, W, R, NT>(pa, mem);
             team_sync();
             if constexpr (STAGED) {
@@ -1054,9 +1057,10 @@ constexpr int kResidCols = 128;  // columns per residual chunk
 // thread, chunk ch = blockIdx.y of kResidCols columns
 template <int PA, int PX>
 __global__ __launch_bounds__(kThreads) void k_resid_part(const double *A, long lda, long psa, int m, int n,
-                                                         const double *x, long xps, double *part)
+                                                         const double *x, long xps, double *part, const int *skip)
 {
     __shared__ double sx[kResidCols * PX];
+    if (*skip) return;
     const int c0 = blockIdx.y * kResidCols;
     const int c1 = (n - c0 < kResidCols) ? n : c0 + kResidCols;
     for (int j = threadIdx.x; j < c1 - c0; j += kThreads) lds_st(&sx[j * PX], ldm<PX>(x, xps, c0 + j));
@@ -1077,8 +1081,9 @@ __global__ __launch_bounds__(kThreads) void k_resid_part(const double *A, long l
 // r_i = b_i - sum_ch part[ch][.][i] (chunks in order)
 template <int PX>
 __global__ __launch_bounds__(kThreads) void k_resid_fin(const double *b, long bps, const double *part, int m, int nch,
-                                                        double *r, long rps)
+                                                        double *r, long rps, const int *skip)
 {
+    if (*skip) return;
     const long i = (long)blockIdx.x * kThreads + threadIdx.x;
     if (i >= m) return;
     Acc<PX> t = acc_from(ldm<PX>(b, bps, i));
@@ -1092,11 +1097,12 @@ __global__ __launch_bounds__(kThreads) void k_resid_fin(const double *b, long bp
 }
 
 // x_i += d_i (d of PD <= PX limbs); norms[0] = max |d_i|, norms[1] = max |x_i| (leading limbs;
-// non-negative doubles ordered as their bit patterns)
+// non-negative doubles ordered as their bit patterns; both zero on entry)
 template <int PX, int PD>
 __global__ __launch_bounds__(kThreads) void k_refine_add(double *x, long xps, const double *d, long dps, int n,
-                                                         unsigned long long *norms)
+                                                         unsigned long long *norms, const int *skip)
 {
+    if (*skip) return;
     const long i = (long)blockIdx.x * kThreads + threadIdx.x;
     if (i >= n) return;
     const V<PD> dv = ldm<PD>(d, dps, i);
@@ -1105,6 +1111,40 @@ __global__ __launch_bounds__(kThreads) void k_refine_add(double *x, long xps, co
     atomicMax(&norms[0], (unsigned long long)__double_as_longlong(fabs(dv.x[0])));
     atomicMax(&norms[1], (unsigned long long)__double_as_longlong(fabs(xn.x[0])));
 }
+
+// After refinement step it: stop (*done = 1) once x has converged to PX limbs, judged from the
+// correction norms d_k = max |d| of the steps so far: converged when d_it <= u max|x|, or when
+// the next correction, estimated from the observed contraction as d_it^2 / d_(it-1), would be
+// below u max|x| (u = 2^-(53 PX - (PX - 1))).  Otherwise the next step's norms are cleared
+// (they hold -1 until a step runs, so the steps taken can be counted).  One thread.
+template <int PX>
+__global__ void k_refine_check(int it, int iters, double *norms, int *done)
+{
+    if (threadIdx.x != 0 || *done) return;
+    const double u = ldexp(1.0, -(53 * PX - (PX - 1)));
+    const double d = norms[2 * it], xm = norms[2 * it + 1];
+    bool conv = d <= u * xm;
+    if (!conv && it > 0) {
+        const double dp = norms[2 * it - 2];
+        conv = dp > 0.0 && d * (d / dp) <= u * xm;
+    }
+    if (conv) {
+        *done = 1;
+    } else if (it + 1 < iters) {
+        norms[2 * it + 2] = 0.0;
+        norms[2 * it + 3] = 0.0;
+    }
+}
+
+namespace {
+// norms := -1 (steps not taken), except step 0's pair := 0; *done := 0
+__global__ void k_refine_init(double *norms, int iters, int *done)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < 2 * iters) norms[i] = (i < 2) ? 0.0 : -1.0;
+    if (i == 0) *done = 0;
+}
+}  // namespace
 
 namespace {
 __global__ void k_zero_f64(double *p, long n)
@@ -1129,6 +1169,15 @@ __global__ void k_copy(const double *src, long sps, double *dst, long dps, int n
         for (int k = 0; k < P; ++k) dst[k * dps + i] = src[k * sps + i];
 }
 
+// k_copy unless *skip
+__global__ void k_copy_if(const double *src, long sps, double *dst, long dps, int n, int P, const int *skip)
+{
+    if (*skip) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        for (int k = 0; k < P; ++k) dst[k * dps + i] = src[k * sps + i];
+}
+
 // *d_info = smallest 1-based i with R(i,i) exactly zero, else 0
 __global__ __launch_bounds__(kThreads) void k_diag_check(const double *R, long ldr, long ps, int n, int P, int *d_info)
 {
@@ -1142,6 +1191,18 @@ __global__ __launch_bounds__(kThreads) void k_diag_check(const double *R, long l
     }
     __syncthreads();
     if (threadIdx.x == 0) *d_info = (smin == INT_MAX) ? 0 : smin + 1;
+}
+
+// A grid barrier of the factorisation timed out (*err != 0): *d_info := -1 (x unspecified)
+__global__ void k_fold_err(const int *err, int *d_info)
+{
+    if (threadIdx.x == 0 && *err != 0) *d_info = -1;
+}
+
+// *d_info := -1 if a grid barrier timed out, else 0
+__global__ void k_set_info(const int *err, int *d_info)
+{
+    if (threadIdx.x == 0) *d_info = (*err != 0) ? -1 : 0;
 }
 }  // namespace
 
@@ -1227,8 +1288,9 @@ __global__ __launch_bounds__(kThreads) void k_invert(InvArgs g)
 // x_i := Xinv_i y_i, one wave per output row
 template <int P>
 __global__ __launch_bounds__(kThreads) void k_bs_xi(const double *Xi, long ldx, long psx, const double *y, long yps,
-                                                   double *x, long xps, int tile)
+                                                   double *x, long xps, int tile, const int *skip)
 {
+    if (skip && *skip) return;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int row = blockIdx.x * 4 + wid;
     if (row >= tile) return;
@@ -1243,10 +1305,11 @@ __global__ __launch_bounds__(kThreads) void k_bs_xi(const double *Xi, long ldx, 
 // split over the 4 waves and combined in a fixed order
 template <int P>
 __global__ __launch_bounds__(kThreads) void k_bs_upd(const double *Rc, long ldr, long psr, const double *xi, long xps,
-                                                    double *y, long yps, int rows, int tile)
+                                                    double *y, long yps, int rows, int tile, const int *skip)
 {
     __shared__ double sx[256 * P];
     __shared__ double sp[4][64 * P];
+    if (skip && *skip) return;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     for (int c = threadIdx.x; c < tile; c += kThreads) lds_st(&sx[c * P], ldm<P>(xi, xps, c));
     __syncthreads();
@@ -1333,8 +1396,9 @@ __global__ __launch_bounds__(kThreads) void k_form_w(const double *A, long lda, 
 // S(l, c) = Y_k(:, l)^T B(kt:, c): one wave per (l, c)
 template <int P>
 __global__ __launch_bounds__(kThreads) void k_tn(const double *Y, long lda, long ps, int h, int tile, const double *B,
-                                                long ldb, long bps, int nrhs, double *S, long sps)
+                                                long ldb, long bps, int nrhs, double *S, long sps, const int *skip)
 {
+    if (skip && *skip) return;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int l = blockIdx.x * 4 + wid, c = blockIdx.y;
     if (l >= tile || c >= nrhs) return;
@@ -1349,8 +1413,9 @@ __global__ __launch_bounds__(kThreads) void k_tn(const double *Y, long lda, long
 // U(i, c) = sum_{l<=i} T(l, i) S(l, c), written over S (U in a separate buffer)
 template <int P>
 __global__ __launch_bounds__(kThreads) void k_trmm_t(const double *T, long ldt, long tps, const double *S, long sps,
-                                                    double *U, int tile, int nrhs)
+                                                    double *U, int tile, int nrhs, const int *skip)
 {
+    if (skip && *skip) return;
     const int i = blockIdx.x * kThreads + threadIdx.x, c = blockIdx.y;
     if (i >= tile || c >= nrhs) return;
     Acc<P> acc = acc_zero<P>();
@@ -1385,8 +1450,9 @@ __global__ void k_identity(double *B, long ldb, long bps, int rows, int cols, in
 // B(kt + r, c) -= sum_l Y_k(r, l) U(l, c)
 template <int P>
 __global__ __launch_bounds__(kThreads) void k_nn_sub(const double *Y, long lda, long ps, int h, int tile, const double *U,
-                                                    long ups, double *B, long ldb, long bps)
+                                                    long ups, double *B, long ldb, long bps, const int *skip)
 {
+    if (skip && *skip) return;
     const long r = (long)blockIdx.x * kThreads + threadIdx.x;
     const int c = blockIdx.y;
     if (r >= h) return;
@@ -1405,15 +1471,29 @@ bool timing_on();
 void timing_begin(hipStream_t s, void **ev);
 void timing_end(hipStream_t s, void *ev, const char *name, int P, double work);
 
-// Side stream and events of the calling host thread on the current device (created on first
-// use, default priority); look-ahead switch and the grid cap of the concurrent update.
+// Side stream and events of the calling host thread on the current device, created by
+// mdls_init (default priority); null when mdls_init has not run on this thread for this device,
+// and then the trailing updates run on the caller's stream.
 struct SideStream {
     hipStream_t q;
     hipEvent_t ev_panel, ev_wide[2];
 };
 SideStream *side_stream();
-bool lookahead_on();
+
+// Process-wide tuning (mdls_set_tuning); the defaults are compile-time constants and nothing is
+// read from the environment.  Only panel_variant changes results (the panel's reduction order).
+struct Tuning {
+    int lookahead;         // 1: trailing updates concurrently on the side stream (when it exists)
+    int panel_variant;     // 0: default panel shape, 1: the alternative shape (more rows per thread)
+    int apply_grid_cap;    // > 0: workgroups of a concurrent trailing update; 0: the built-in rule
+    int apply_wide_rows;   // od: trailing updates of at least this many rows take two workgroups per CU
+    unsigned spin_limit;   // polls before a grid barrier gives up
+};
+Tuning tuning();
 int apply_grid_cap(int P, int h);
+// Workgroups of the panel kernel of precision P (current variant) that can be resident at once on
+// the current device (occupancy x compute units); 0 if the device cannot be queried.
+int panel_capacity(int P);
 
 #define MDLS_LAUNCH(NAME, PREC, WORK, KERNEL, GRID, BLOCK, STREAM, ...)                       \
     do {                                                                                     \
@@ -1518,28 +1598,27 @@ struct PanelCfg {
     int nt, r;
 };
 
-// Threads per workgroup and rows per thread of the panel kernel; MDLS_PANEL_CFG="nt,r"
-// overrides (one of the instantiated pairs).
-inline PanelCfg panel_cfg(int P)
+// Threads per workgroup and rows per thread of the panel kernel: variant 0 (default) or 1 (the
+// alternative shape, for tests of the multi-workgroup path and for tuning).
+inline PanelCfg panel_cfg(int P, int variant)
 {
-    PanelCfg d;
     switch (P) {
-    case 1: d = {512, 2}; break;
-    case 2: d = {512, 2}; break;
-    case 4: d = {256, 1}; break;
-    default: d = {256, 1}; break;
+    case 1:
+    case 2: return variant ? PanelCfg{512, 8} : PanelCfg{512, 2};
+    case 4: return variant ? PanelCfg{256, 4} : PanelCfg{256, 1};
+    default: return variant ? PanelCfg{256, 2} : PanelCfg{256, 1};
     }
-    const char *e = getenv("MDLS_PANEL_CFG");
-    if (e) {
-        PanelCfg o{0, 0};
-        if (sscanf(e, "%d,%d", &o.nt, &o.r) == 2) {
-            const bool ok = (P <= 2 && ((o.nt == 512 && o.r == 8) || (o.nt == 512 && o.r == 2))) ||
-                            (P == 4 && o.nt == 256 && (o.r == 4 || o.r == 1)) ||
-                            (P == 8 && o.nt == 256 && (o.r == 1 || o.r == 2));
-            if (ok) d = o;
-        }
-    }
-    return d;
+}
+
+inline PanelCfg panel_cfg(int P) { return panel_cfg(P, tuning().panel_variant); }
+
+// Workgroups of the largest panel launch of an m-row factorisation.
+inline int panel_groups(int P, int m)
+{
+    const PanelCfg cf = panel_cfg(P);
+    const int rows_per_wg = cf.nt / leaf_width(P) * cf.r;
+    const int g = (m + rows_per_wg - 1) / rows_per_wg;
+    return g < 1 ? 1 : g;
 }
 
 template <int P, int W>
@@ -1563,6 +1642,29 @@ void launch_panel(const PanelArgs &a, PanelCfg cf, hipStream_t s)
         MDLS_PANEL_CASE(256, 2)
     }
 #undef MDLS_PANEL_CASE
+}
+
+// Resident workgroups per CU of the panel kernel of shape cf (0 if the query fails).
+template <int P>
+int panel_occupancy_t(PanelCfg cf)
+{
+    constexpr int W = Cfg<P>::W;
+    int per_cu = 0;
+    hipError_t e = hipErrorInvalidValue;
+#define MDLS_OCC_CASE(NT_, R_) \
+    if (cf.nt == NT_ && cf.r == R_) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_panel<P, W, R_, NT_>, NT_, 0);
+    if constexpr (P <= 2) {
+        MDLS_OCC_CASE(512, 8)
+        MDLS_OCC_CASE(512, 2)
+    } else if constexpr (P == 4) {
+        MDLS_OCC_CASE(256, 4)
+        MDLS_OCC_CASE(256, 1)
+    } else {
+        MDLS_OCC_CASE(256, 1)
+        MDLS_OCC_CASE(256, 2)
+    }
+#undef MDLS_OCC_CASE
+    return e == hipSuccess ? per_cu : 0;
 }
 
 // Householder QR of A (m x n) in narrow panels; B (nb columns, may be null) receives Q^T B.
@@ -1609,10 +1711,11 @@ int qr_panels(const Ctx<P> &cx, int m, int n, double *A, long lda, long psa, dou
     const PanelCfg cf = panel_cfg(P);
     const int rows_per_wg = cf.nt / W * cf.r;
     const int nleaves = cx.L.nleaves;
+    const Tuning tu = tuning();
     MDLS_LAUNCH("k_zero", P, 0, k_zero_u32, dim3((nleaves + 1 + 255) / 256), dim3(256), cx.s, cx.ctr(), nleaves + 1);
     MDLS_LAUNCH("k_zero", P, 0, k_zero_u32, dim3(1), dim3(256), cx.s, (unsigned *)cx.err(), 4);
     const long tps = (long)W * W * nleaves;
-    SideStream *ss = (nleaves > 1 && lookahead_on()) ? side_stream() : nullptr;
+    SideStream *ss = (nleaves > 1 && tu.lookahead) ? side_stream() : nullptr;
     for (int l = 0; l < nleaves; ++l) {
         const int c0 = l * W;
         const int wact = (n - c0 < W) ? (n - c0) : W;
@@ -1634,6 +1737,7 @@ int qr_panels(const Ctx<P> &cx, int m, int n, double *A, long lda, long psa, dou
         pa.gpart = cx.gpart();
         pa.gbar = cx.ctr() + l;
         pa.err = cx.err();
+        pa.spin = tu.spin_limit;
         int G = (h + off + rows_per_wg - 1) / rows_per_wg;
         if (G < 1) G = 1;
         pa.G = G;
@@ -1686,14 +1790,14 @@ void invert_tiles(const Ctx<P> &cx, const InvArgs &ia, int ntiles)
                 dim3(kThreads), cx.s, ia);
 }
 
-// tiled back substitution on y (P planes of n, in ws.yw); x receives the solution
+// Stage 1 of the tiled back substitution (Algorithm 1): *d_info from R's diagonal, and the
+// inverses of the n / tile diagonal tiles into Xinv (tile t at Xinv + t tile^2, ld tile, plane
+// stride tile n).
 template <int P>
-void backsub_tiles(const Ctx<P> &cx, int n, int tile, const double *R, long ldr, long psr, double *x, long xps,
-                   int *d_info)
+void backsub_prep(const Ctx<P> &cx, int n, int tile, const double *R, long ldr, long psr, double *Xinv, int *d_info)
 {
     const int N = n / tile;
     MDLS_LAUNCH("k_diag_check", P, 0, k_diag_check, dim3(1), dim3(kThreads), cx.s, R, ldr, psr, n, P, d_info);
-    double *Xinv = cx.big();
     const long xips = (long)tile * n;
     InvArgs ia;
     ia.U = R;
@@ -1708,20 +1812,36 @@ void backsub_tiles(const Ctx<P> &cx, int n, int tile, const double *R, long ldr,
     ia.xstride = (long)tile * tile;
     ia.tile = tile;
     invert_tiles<P>(cx, ia, N);
-    double *y = cx.yw();
+}
+
+// Stage 2 (Algorithm 1): for i = N-1 .. 0, x_i := U_i^-1 y_i, then y_j -= R_{j,i} x_i for every
+// j < i; y (P planes of n) is overwritten.  Every kernel returns at once while *skip is set.
+template <int P>
+void backsub_sweep(const Ctx<P> &cx, int n, int tile, const double *R, long ldr, long psr, const double *Xinv,
+                   double *y, double *x, long xps, const int *skip)
+{
+    const int N = n / tile;
+    const long xips = (long)tile * n;
     const long yps = n;
     for (int i = N - 1; i >= 0; --i) {
         const long it = (long)i * tile;
         MDLS_LAUNCH("k_bs_xi", P, 0.5 * tile * tile, (k_bs_xi<P>), dim3((tile + 3) / 4), dim3(kThreads), cx.s,
-                    Xinv + (long)i * tile * tile,
-                           (long)tile, xips, y + it, yps, x + it, xps, tile);
+                    Xinv + (long)i * tile * tile, (long)tile, xips, y + it, yps, x + it, xps, tile, skip);
         if (i > 0) {
             const int rows = i * tile;
             MDLS_LAUNCH("k_bs_upd", P, (double)rows * tile, (k_bs_upd<P>), dim3((rows + 63) / 64), dim3(kThreads), cx.s,
-                        R + it * ldr, ldr, psr,
-                               x + it, xps, y, yps, rows, tile);
+                        R + it * ldr, ldr, psr, x + it, xps, y, yps, rows, tile, skip);
         }
     }
+}
+
+// tiled back substitution of y (P planes of n, in ws.yw); x receives the solution
+template <int P>
+void backsub_tiles(const Ctx<P> &cx, int n, int tile, const double *R, long ldr, long psr, double *x, long xps,
+                   int *d_info)
+{
+    backsub_prep<P>(cx, n, tile, R, ldr, psr, cx.big(), d_info);
+    backsub_sweep<P>(cx, n, tile, R, ldr, psr, cx.big(), cx.yw(), x, xps, nullptr);
 }
 
 template <int P>
@@ -1732,15 +1852,21 @@ int solve_t(int m, int n, int tile, double *A, int lda, double *b, double *x, vo
     if (qr_panels<P>(cx, m, n, A, lda, psa, b, m, m, 1) != 0) return MDLS_EHIP;
     MDLS_LAUNCH("k_copy", P, 0, k_copy, dim3((n + 255) / 256), dim3(256), s, b, (long)m, cx.yw(), (long)n, n, P);
     backsub_tiles<P>(cx, n, tile, A, lda, psa, x, n, d_info);
+    MDLS_LAUNCH("k_fold_err", P, 0, k_fold_err, dim3(1), dim3(64), s, cx.err(), d_info);
     return hipGetLastError() == hipSuccess ? 0 : MDLS_EHIP;
 }
 
 template <int P>
-int qr_t(int m, int n, int tile, double *A, int lda, double *T, int ldt, void *ws, hipStream_t s)
+int qr_t(int m, int n, int tile, double *A, int lda, double *beta, double *T, int ldt, void *ws, int *d_info,
+         hipStream_t s)
 {
     Ctx<P> cx{(char *)ws, layout(P, m, n, tile), s};
     const long psa = (long)lda * n;
     if (qr_panels<P>(cx, m, n, A, lda, psa, nullptr, 0, 0, 0) != 0) return MDLS_EHIP;
+    if (beta)
+        MDLS_LAUNCH("k_copy", P, 0, k_copy, dim3((n + 255) / 256), dim3(256), s, cx.beta(), (long)n, beta, (long)n, n,
+                    P);
+    if (d_info) MDLS_LAUNCH("k_set_info", P, 0, k_set_info, dim3(1), dim3(64), s, cx.err(), d_info);
     if (T) {
         const int N = n / tile;
         double *G = cx.big();
@@ -1763,14 +1889,14 @@ int qr_t(int m, int n, int tile, double *A, int lda, double *T, int ldt, void *w
     return hipGetLastError() == hipSuccess ? 0 : MDLS_EHIP;
 }
 
+// B := Q^T B by the tile blocks in order, B := B - Y_k T_k^T (Y_k^T B), 64 columns of B at a
+// time; S and U are scratch of P tile 64 doubles each.  Every kernel returns at once while
+// *skip is set (skip may be null).
 template <int P>
-int apply_qt_t(int m, int n, int tile, const double *A, int lda, const double *T, int ldt, double *B, int ldb, int nrhs,
-               void *ws, hipStream_t s)
+void apply_qt_blocks(int m, int n, int tile, const double *A, int lda, const double *T, int ldt, double *B, int ldb,
+                     int nrhs, double *S, double *U, const int *skip, hipStream_t s)
 {
-    Ctx<P> cx{(char *)ws, layout(P, m, n, tile), s};
     const long psa = (long)lda * n, tps = (long)ldt * n, bps = (long)ldb * nrhs;
-    double *S = cx.big();
-    double *U = S + (size_t)P * tile * 64;
     const long sps = (long)tile * 64;
     const int N = n / tile;
     for (int c0 = 0; c0 < nrhs; c0 += 64) {
@@ -1781,16 +1907,22 @@ int apply_qt_t(int m, int n, int tile, const double *A, int lda, const double *T
             const double *Y = A + kt * lda + kt;
             const int h = m - (int)kt;
             MDLS_LAUNCH("k_tn", P, (double)h * tile * nc, (k_tn<P>), dim3((tile + 3) / 4, nc), dim3(kThreads), s, Y,
-                        (long)lda, psa, h, tile,
-                               Bc + kt, (long)ldb, bps, nc, S, sps);
+                        (long)lda, psa, h, tile, Bc + kt, (long)ldb, bps, nc, S, sps, skip);
             MDLS_LAUNCH("k_trmm_t", P, 0.5 * tile * tile * nc, (k_trmm_t<P>), dim3((tile + kThreads - 1) / kThreads, nc),
-                        dim3(kThreads), s,
-                               T + kt * ldt, (long)ldt, tps, S, sps, U, tile, nc);
+                        dim3(kThreads), s, T + kt * ldt, (long)ldt, tps, S, sps, U, tile, nc, skip);
             MDLS_LAUNCH("k_nn_sub", P, (double)h * tile * nc, (k_nn_sub<P>), dim3((h + kThreads - 1) / kThreads, nc),
-                        dim3(kThreads), s, Y,
-                               (long)lda, psa, h, tile, U, sps, Bc + kt, (long)ldb, bps);
+                        dim3(kThreads), s, Y, (long)lda, psa, h, tile, U, sps, Bc + kt, (long)ldb, bps, skip);
         }
     }
+}
+
+template <int P>
+int apply_qt_t(int m, int n, int tile, const double *A, int lda, const double *T, int ldt, double *B, int ldb, int nrhs,
+               void *ws, hipStream_t s)
+{
+    Ctx<P> cx{(char *)ws, layout(P, m, n, tile), s};
+    double *S = cx.big();
+    apply_qt_blocks<P>(m, n, tile, A, lda, T, ldt, B, ldb, nrhs, S, S + (size_t)P * tile * 64, nullptr, s);
     return hipGetLastError() == hipSuccess ? 0 : MDLS_EHIP;
 }
 
@@ -1814,11 +1946,11 @@ int apply_q_t(int m, int n, int tile, const double *A, int lda, const double *T,
             const double *Y = A + kt * lda + kt;
             const int h = m - (int)kt;
             MDLS_LAUNCH("k_tn", P, (double)h * tile * nc, (k_tn<P>), dim3((tile + 3) / 4, nc), dim3(kThreads), s, Y,
-                        (long)lda, psa, h, tile, Bc + kt, (long)ldb, bps, nc, S, sps);
+                        (long)lda, psa, h, tile, Bc + kt, (long)ldb, bps, nc, S, sps, nullptr);
             MDLS_LAUNCH("k_trmm_n", P, 0.5 * tile * tile * nc, (k_trmm_n<P>), dim3((tile + kThreads - 1) / kThreads, nc),
                         dim3(kThreads), s, T + kt * ldt, (long)ldt, tps, S, sps, U, tile, nc);
             MDLS_LAUNCH("k_nn_sub", P, (double)h * tile * nc, (k_nn_sub<P>), dim3((h + kThreads - 1) / kThreads, nc),
-                        dim3(kThreads), s, Y, (long)lda, psa, h, tile, U, sps, Bc + kt, (long)ldb, bps);
+                        dim3(kThreads), s, Y, (long)lda, psa, h, tile, U, sps, Bc + kt, (long)ldb, bps, nullptr);
         }
     }
     return hipGetLastError() == hipSuccess ? 0 : MDLS_EHIP;
@@ -1952,6 +2084,7 @@ int batch_solve_t(int count, double *A, double *b, double *x, int variant, void 
     a.scratch = (double *)(w + L.scratch);
     a.counter = (unsigned *)(w + L.ctr);
     a.err = (int *)(w + L.ctr) + 1;
+    a.spin = tuning().spin_limit;
     a.tctr = (unsigned *)(w + L.tctr);
     a.xch = (double *)(w + L.xch);
     a.info = d_info;
@@ -1977,14 +2110,18 @@ int batch_solve_t(int count, double *A, double *b, double *x, int variant, void 
 
 // ---------------------------------------------------------------- refined solve (host)
 // Least squares to PX limbs from a double-double factorisation: F := A, QR of F in dd (with
-// the tile T factors), x := 0, r := b; then `iters` times: d := R^-1 (Q^T r)(0:n) in dd (r
-// rounded to dd), x += d, r := b - A x in PX limbs.  Converges when kappa(A) 2^-105 << 1;
-// norms[2 it], norms[2 it + 1] receive max |d| and max |x| of iteration it.
+// the tile T factors), the inverses of R's diagonal tiles (once), x := 0, r := b; then at most
+// `iters` steps: d := R^-1 (Q^T r)(0:n) in dd (r rounded to dd), x += d, r := b - A x in PX limbs,
+// stopping on the device once the correction norms show convergence (k_refine_check; the
+// remaining steps' kernels return at once, so the call stays asynchronous).  Converges when
+// kappa(A) 2^-105 << 1; norms[2 it], norms[2 it + 1] receive max |d| and max |x| of step it, -1
+// for steps not taken.
 inline size_t refine_extra_bytes(int px, int m, int n, int tile)
 {
     const size_t nch = (size_t)(n + kResidCols - 1) / kResidCols;
-    return sizeof(double) * (2 * (size_t)n * tile + (size_t)px * m + 2 * (size_t)m + 2 * (size_t)n + nch * px * m) +
-           5 * 256;
+    return sizeof(double) * (2 * (size_t)n * tile + (size_t)px * m + 2 * (size_t)m + 2 * (size_t)n + nch * px * m +
+                             4 * (size_t)tile * 64) +
+           7 * 256;
 }
 
 template <int PX>
@@ -1992,41 +2129,48 @@ int refine_t(int m, int n, int tile, const double *A, int lda, const double *b, 
              void *ws, int *d_info, double *norms, hipStream_t s)
 {
     const Layout L = layout(2, m, n, tile);
+    Ctx<2> cx{(char *)ws, L, s};
     char *e = (char *)ws + align256(L.total);
-    auto take = [&](size_t doubles) {
-        double *p = (double *)e;
-        e += align256(sizeof(double) * doubles);
+    auto take = [&](size_t bytes) {
+        char *p = e;
+        e += align256(bytes);
         return p;
     };
     const int nch = (n + kResidCols - 1) / kResidCols;
-    double *T = take(2 * (size_t)n * tile);
-    double *r = take((size_t)PX * m);
-    double *rdd = take(2 * (size_t)m);
-    double *dd = take(2 * (size_t)n);
-    double *part = take((size_t)nch * PX * m);
+    double *T = (double *)take(sizeof(double) * 2 * (size_t)n * tile);
+    double *r = (double *)take(sizeof(double) * (size_t)PX * m);
+    double *rdd = (double *)take(sizeof(double) * 2 * (size_t)m);
+    double *dd = (double *)take(sizeof(double) * 2 * (size_t)n);
+    double *part = (double *)take(sizeof(double) * (size_t)nch * PX * m);
+    double *S = (double *)take(sizeof(double) * 4 * (size_t)tile * 64);
+    int *done = (int *)take(sizeof(int) * 4);
+    double *U = S + 2 * (size_t)tile * 64;
     const long psa = (long)lda * n;
     MDLS_LAUNCH("k_copy", PX, 0, k_copy, dim3((unsigned)((psa + 255) / 256)), dim3(256), s, A, psa, F, psa, (int)psa, 2);
     MDLS_LAUNCH("k_copy", PX, 0, k_copy, dim3((m + 255) / 256), dim3(256), s, b, (long)m, r, (long)m, m, PX);
     MDLS_LAUNCH("k_zero", PX, 0, k_zero_f64, dim3((PX * n + 255) / 256), dim3(256), s, x, (long)PX * n);
-    MDLS_LAUNCH("k_zero", PX, 0, k_zero_f64, dim3((2 * iters + 255) / 256), dim3(256), s, norms, (long)2 * iters);
-    int rc = qr_t<2>(m, n, tile, F, lda, T, tile, ws, s);
-    for (int it = 0; it < iters && rc == 0; ++it) {
+    MDLS_LAUNCH("k_refine_init", PX, 0, k_refine_init, dim3((2 * iters + 255) / 256), dim3(256), s, norms, iters, done);
+    int rc = qr_t<2>(m, n, tile, F, lda, nullptr, T, tile, ws, nullptr, s);
+    if (rc != 0) return rc;
+    double *Xinv = cx.big();
+    backsub_prep<2>(cx, n, tile, F, lda, psa, Xinv, d_info);
+    for (int it = 0; it < iters; ++it) {
         if (it > 0) {
             MDLS_LAUNCH("k_resid_part", PX, (double)m * n, (k_resid_part<2, PX>), dim3((m + kThreads - 1) / kThreads, nch),
-                        dim3(kThreads), s, A, (long)lda, psa, m, n, x, (long)n, part);
+                        dim3(kThreads), s, A, (long)lda, psa, m, n, x, (long)n, part, done);
             MDLS_LAUNCH("k_resid_fin", PX, 0, (k_resid_fin<PX>), dim3((m + kThreads - 1) / kThreads), dim3(kThreads), s, b,
-                        (long)m, part, m, nch, r, (long)m);
+                        (long)m, part, m, nch, r, (long)m, done);
         }
-        MDLS_LAUNCH("k_copy", PX, 0, k_copy, dim3((m + 255) / 256), dim3(256), s, r, (long)m, rdd, (long)m, m, 2);
-        rc = apply_qt_t<2>(m, n, tile, F, lda, T, tile, rdd, m, 1, ws, s);
-        if (rc != 0) break;
-        MDLS_LAUNCH("k_copy", PX, 0, k_copy, dim3((n + 255) / 256), dim3(256), s, rdd, (long)m, dd, (long)n, n, 2);
-        rc = backsub_t<2>(n, tile, F, lda, dd, ws, d_info, s);
-        if (rc != 0) break;
+        MDLS_LAUNCH("k_copy", PX, 0, k_copy_if, dim3((m + 255) / 256), dim3(256), s, r, (long)m, rdd, (long)m, m, 2, done);
+        apply_qt_blocks<2>(m, n, tile, F, lda, T, tile, rdd, m, 1, S, U, done, s);
+        MDLS_LAUNCH("k_copy", PX, 0, k_copy_if, dim3((n + 255) / 256), dim3(256), s, rdd, (long)m, cx.yw(), (long)n, n, 2,
+                    done);
+        backsub_sweep<2>(cx, n, tile, F, lda, psa, Xinv, cx.yw(), dd, n, done);
         MDLS_LAUNCH("k_refine_add", PX, 0, (k_refine_add<PX, 2>), dim3((n + kThreads - 1) / kThreads), dim3(kThreads), s,
-                    x, (long)n, dd, (long)n, n, (unsigned long long *)(norms + 2 * it));
+                    x, (long)n, dd, (long)n, n, (unsigned long long *)(norms + 2 * it), done);
+        MDLS_LAUNCH("k_refine_check", PX, 0, (k_refine_check<PX>), dim3(1), dim3(64), s, it, iters, norms, done);
     }
-    if (rc != 0) return rc;
+    MDLS_LAUNCH("k_fold_err", PX, 0, k_fold_err, dim3(1), dim3(64), s, cx.err(), d_info);
     return hipGetLastError() == hipSuccess ? 0 : MDLS_EHIP;
 }
 
@@ -2036,7 +2180,7 @@ int refine_t(int m, int n, int tile, const double *A, int lda, const double *b, 
 
 #define MDLS_FOR_PRECISION(X, P)                                                                        \
     X template int solve_t<P>(int, int, int, double *, int, double *, double *, void *, int *, hipStream_t);     \
-    X template int qr_t<P>(int, int, int, double *, int, double *, int, void *, hipStream_t);                 \
+    X template int qr_t<P>(int, int, int, double *, int, double *, double *, int, void *, int *, hipStream_t); \
     X template int apply_qt_t<P>(int, int, int, const double *, int, const double *, int, double *, int, int,   \
                                  void *, hipStream_t);                                                         \
     X template int form_w_t<P>(int, int, int, const double *, int, const double *, int, double *, int,         \
@@ -2045,6 +2189,7 @@ int refine_t(int m, int n, int tile, const double *A, int lda, const double *b, 
     X template int apply_q_t<P>(int, int, int, const double *, int, const double *, int, double *, int, int,    \
                                 void *, hipStream_t);                                                          \
     X template int form_q_t<P>(int, int, int, const double *, int, const double *, int, double *, int, int,     \
-                               void *, hipStream_t);
+                               void *, hipStream_t);                                                          \
+    X template int panel_occupancy_t<P>(PanelCfg);
 
 }  // namespace mdls_impl

@@ -16,9 +16,11 @@ _LIB_PATH = os.path.join(_HERE, "libmdls.so")
 
 MDLS_F64, MDLS_DD, MDLS_QD, MDLS_OD = 1, 2, 4, 8
 MDLS_EHIP, MDLS_EUNSUPPORTED = -100, -101
+MDLS_TUNE_LOOKAHEAD, MDLS_TUNE_PANEL_VARIANT, MDLS_TUNE_APPLY_GRID_CAP = 1, 2, 3
+MDLS_TUNE_APPLY_WIDE_ROWS, MDLS_TUNE_SPIN_LIMIT = 4, 5
 
 # every symbol include/mdls.h declares
-EXPORTS = ("mdls_max_rows", "mdls_workspace_bytes", "mdls_qr", "mdls_apply_qt", "mdls_form_w",
+EXPORTS = ("mdls_init", "mdls_finalize", "mdls_set_tuning", "mdls_get_tuning", "mdls_max_rows", "mdls_workspace_bytes", "mdls_qr", "mdls_apply_qt", "mdls_form_w",
            "mdls_backsub", "mdls_solve", "mdls_status_string", "mdls_timing_enable", "mdls_timing_reset",
            "mdls_timing_query", "mdls_timing_kernels", "mdls_batch_workspace_bytes", "mdls_batch_plan",
            "mdls_solve_batched", "mdls_batch_variants", "mdls_batch_autotune", "mdls_wall_clock_khz",
@@ -48,11 +50,16 @@ def lib():
                             "there is no CPU fallback")
         L = ctypes.CDLL(_LIB_PATH)
         i, sz, vp = ctypes.c_int, ctypes.c_size_t, ctypes.c_void_p
+        L.mdls_init.argtypes = []
+        L.mdls_finalize.argtypes = []
+        L.mdls_set_tuning.argtypes = [i, ctypes.c_long]
+        L.mdls_get_tuning.argtypes = [i]
+        L.mdls_get_tuning.restype = ctypes.c_long
         L.mdls_max_rows.argtypes = [i]
         L.mdls_max_rows.restype = i
         L.mdls_workspace_bytes.argtypes = [i, i, i, i]
         L.mdls_workspace_bytes.restype = sz
-        L.mdls_qr.argtypes = [i, i, i, i, vp, i, vp, i, vp, sz, vp]
+        L.mdls_qr.argtypes = [i, i, i, i, vp, i, vp, vp, i, vp, sz, vp, vp]
         L.mdls_apply_qt.argtypes = [i, i, i, i, vp, i, vp, i, vp, i, i, vp, sz, vp]
         L.mdls_form_w.argtypes = [i, i, i, i, vp, i, vp, i, vp, i, vp]
         L.mdls_apply_q.argtypes = [i, i, i, i, vp, i, vp, i, vp, i, i, vp, sz, vp]
@@ -88,7 +95,7 @@ def lib():
         L.mdls_dd_gemm_tn_workspace_bytes.argtypes = [i, i]
         L.mdls_dd_gemm_tn_workspace_bytes.restype = sz
         L.mdls_dd_gemm_tn.argtypes = [i, i, i, i, vp, i, vp, i, vp, i, vp, sz, vp]
-        for f in ("mdls_capply_q", "mdls_cform_q", "mdls_dd_gemm_tn", "mdls_cqr", "mdls_capply_qh", "mdls_cbacksub", "mdls_csolve", "mdls_qr", "mdls_apply_qt", "mdls_apply_q", "mdls_form_q", "mdls_form_w", "mdls_backsub",
+        for f in ("mdls_init", "mdls_finalize", "mdls_set_tuning", "mdls_capply_q", "mdls_cform_q", "mdls_dd_gemm_tn", "mdls_cqr", "mdls_capply_qh", "mdls_cbacksub", "mdls_csolve", "mdls_qr", "mdls_apply_qt", "mdls_apply_q", "mdls_form_q", "mdls_form_w", "mdls_backsub",
                   "mdls_solve", "mdls_timing_enable", "mdls_timing_reset", "mdls_timing_query", "mdls_timing_kernels",
                   "mdls_batch_plan", "mdls_solve_batched", "mdls_batch_variants", "mdls_batch_autotune",
                   "mdls_wall_clock_khz", "mdls_solve_refined"):
@@ -134,6 +141,23 @@ def _vec(t, P, name, length):
         raise ValueError("%s must be a contiguous float64 GPU tensor of shape (%d, %d)" % (name, P, length))
 
 
+def init():
+    """mdls_init on the calling thread and the current device (the look-ahead side stream)."""
+    _check(lib().mdls_init(), "mdls_init")
+
+
+def finalize():
+    _check(lib().mdls_finalize(), "mdls_finalize")
+
+
+def set_tuning(option: int, value: int):
+    _check(lib().mdls_set_tuning(option, value), "mdls_set_tuning")
+
+
+def get_tuning(option: int) -> int:
+    return lib().mdls_get_tuning(option)
+
+
 def max_rows(p: int) -> int:
     return lib().mdls_max_rows(p)
 
@@ -151,15 +175,19 @@ def workspace(p: int, m: int, n: int, tile: int, device="cuda"):
     return torch.empty(nb, dtype=torch.uint8, device=device)
 
 
-def qr(p: int, A, tile: int, T=None, ws=None):
-    """In-place QR of A (P, n, m); T (P, n, ldt) or None receives the tile T factors."""
+def qr(p: int, A, tile: int, T=None, ws=None, beta=None, info=None):
+    """In-place QR of A (P, n, m); T (P, n, ldt) or None receives the tile T factors, beta (P, n)
+    or None the betas, info (one int32) or None the barrier status."""
     m, n = _mat(A, p, "A")
     if ws is None:
         ws = workspace(p, m, n, tile, A.device)
     ldt = 0
     if T is not None:
         ldt, _ = _mat(T, p, "T")
-    rc = lib().mdls_qr(p, m, n, tile, _ptr(A), m, _ptr(T), ldt, _ptr(ws), ws.numel(), _stream())
+    if beta is not None:
+        _vec(beta, p, "beta", n)
+    rc = lib().mdls_qr(p, m, n, tile, _ptr(A), m, _ptr(beta), _ptr(T), ldt, _ptr(ws), ws.numel(), _ptr(info),
+                       _stream())
     _check(rc, "mdls_qr")
     return A, T
 
@@ -491,9 +519,9 @@ def refined_workspace(p_out: int, m: int, n: int, tile: int, device="cuda"):
 
 
 def solve_refined(p_out: int, A, b, tile: int, iters: int, x=None, F=None, ws=None, info=None, norms=None):
-    """x (p_out, n) from a double-double factorisation of A (2, n, m) and iters refinement steps
-    with residuals in p_out limbs; b (p_out, m).  Returns (x, info, norms); norms (2 iters) holds
-    max |correction| and max |x| per step."""
+    """x (p_out, n) from a double-double factorisation of A (2, n, m) and at most iters refinement
+    steps with residuals in p_out limbs; b (p_out, m).  Returns (x, info, norms); norms (2 iters)
+    holds max |correction| and max |x| per step taken, -1 for steps not taken."""
     import torch
 
     m, n = _mat(A, 2, "A")

@@ -69,8 +69,10 @@ def test_other_entry_point_errors(L):
     vp = ctypes.c_void_p
     d = vp(16)
     ws = L.mdls_workspace_bytes(4, 64, 32, 16)
-    assert L.mdls_qr(4, 64, 32, 12, d, 64, d, 12, d, ws, None) == -4  # T wants n % tile == 0
-    assert L.mdls_qr(4, 64, 32, 16, d, 64, d, 8, d, ws, None) == -8  # ldt < tile
+    assert L.mdls_qr(4, 64, 32, 12, d, 64, None, d, 12, d, ws, None, None) == -4  # T wants n % tile == 0
+    assert L.mdls_qr(4, 64, 32, 16, d, 64, None, d, 8, d, ws, None, None) == -9  # ldt < tile
+    assert L.mdls_qr(4, 64, 32, 16, d, 64, None, d, 16, None, ws, None, None) == -10
+    assert L.mdls_qr(4, 64, 32, 16, d, 64, None, d, 16, d, ws - 1, None, None) == -11
     assert L.mdls_backsub(4, 30, 16, d, 30, d, d, ws, d, None) == -3
     assert L.mdls_backsub(4, 32, 16, d, 31, d, d, ws, d, None) == -5
     assert L.mdls_backsub(4, 32, 16, d, 32, d, d, ws, None, None) == -9
@@ -79,6 +81,35 @@ def test_other_entry_point_errors(L):
     assert L.mdls_form_w(4, 64, 32, 16, d, 64, d, 16, d, 63, None) == -10
     assert L.mdls_status_string(0) == b"success"
     assert b"invalid" in L.mdls_status_string(-3)
+
+
+def test_tuning_options(L):
+    """Tuning is explicit (no environment variables): defaults, range checks, round trip."""
+    from paper_2110_08375_amd import mdls
+
+    assert L.mdls_get_tuning(mdls.MDLS_TUNE_LOOKAHEAD) == 1
+    assert L.mdls_get_tuning(mdls.MDLS_TUNE_PANEL_VARIANT) == 0
+    assert L.mdls_get_tuning(mdls.MDLS_TUNE_SPIN_LIMIT) == 1 << 22
+    assert L.mdls_get_tuning(99) == -1
+    assert L.mdls_set_tuning(99, 0) == -1
+    assert L.mdls_set_tuning(mdls.MDLS_TUNE_PANEL_VARIANT, 2) == -2
+    assert L.mdls_set_tuning(mdls.MDLS_TUNE_SPIN_LIMIT, -1) == -2
+    rows0 = L.mdls_max_rows(2)
+    assert L.mdls_set_tuning(mdls.MDLS_TUNE_PANEL_VARIANT, 1) == 0
+    assert L.mdls_max_rows(2) == 4 * rows0  # 512 x 8 instead of 512 x 2 threads x rows
+    assert L.mdls_set_tuning(mdls.MDLS_TUNE_PANEL_VARIANT, 0) == 0
+    assert L.mdls_max_rows(2) == rows0
+    assert L.mdls_set_tuning(mdls.MDLS_TUNE_SPIN_LIMIT, 7) == 0
+    assert L.mdls_get_tuning(mdls.MDLS_TUNE_SPIN_LIMIT) == 7
+    assert L.mdls_set_tuning(mdls.MDLS_TUNE_SPIN_LIMIT, 1 << 22) == 0
+
+
+def test_no_environment_reads():
+    """The library source reads no environment variable."""
+    import glob
+
+    for f in glob.glob(os.path.join(ROOT, "paper_2110_08375_amd", "csrc", "*")):
+        assert "getenv" not in open(f).read(), f
 
 
 def test_binding_refuses_cpu_tensors(L):

@@ -4,7 +4,9 @@ on seeded synthetic inputs.
 Tolerance (forward error of x): ||x_gpu - x_ref|| / ||x_ref|| <= TOL[P] * max(1, kappa_2(A)),
 with TOL = 1e-28 (dd), 1e-58 (qd), 1e-118 (od) and kappa_2 from the leading limbs in FP64.
 The unit roundoffs are 2^-105, 2^-209 and 2^-417, so the tolerance leaves room for the
-O(n) growth of rounding errors in QR and back substitution.
+O(n) growth of rounding errors in QR and back substitution.  Beside it, the headline-size
+comparisons apply a tight bound, err <= 64 n u_P kappa (u_P = 2^-(53P - P + 1)), which a loss
+of 20 low-order bits anywhere in the path would break, and print err / (u_P kappa).
 """
 import os
 
@@ -19,6 +21,11 @@ pytestmark = pytest.mark.gpu
 TOL = {1: 1e-12, 2: 1e-28, 4: 1e-58, 8: 1e-118}
 
 
+def unit(P):
+    """u_P = 2^-(53P - (P - 1)) (the tolerance unit of each precision)"""
+    return 2.0 ** -(53 * P - (P - 1))
+
+
 def dev():
     assert torch.cuda.is_available(), "GPU tests need a GPU"
     return torch.device("cuda:0")
@@ -29,6 +36,8 @@ def M():
     import paper_2110_08375_amd as M
 
     M.lib()  # raises if the HIP library is missing: there is no fallback
+    torch.zeros(1, device=dev())
+    M.init()  # the look-ahead side stream of this thread
     return M
 
 
@@ -94,26 +103,41 @@ def test_solve_matches_oracle(M, orc, P, m, n, tile, ones):
     assert qerr <= TOL[P] * max(1, k)
 
 
-@pytest.mark.parametrize("P,cfg", [(2, "512,2"), (4, "256,1"), (8, "256,2"), (8, "256,1")])
-def test_multi_workgroup_panel(M, orc, monkeypatch, P, cfg):
+@pytest.fixture
+def tuning(M):
+    """set_tuning inside a test; every option is restored afterwards"""
+    from paper_2110_08375_amd import mdls
+
+    opts = (mdls.MDLS_TUNE_LOOKAHEAD, mdls.MDLS_TUNE_PANEL_VARIANT, mdls.MDLS_TUNE_APPLY_GRID_CAP,
+            mdls.MDLS_TUNE_APPLY_WIDE_ROWS, mdls.MDLS_TUNE_SPIN_LIMIT)
+    saved = {o: M.get_tuning(o) for o in opts}
+    yield M.set_tuning
+    torch.cuda.synchronize()
+    for o, v in saved.items():
+        M.set_tuning(o, v)
+
+
+@pytest.mark.parametrize("P,variant", [(2, 0), (4, 0), (8, 1), (8, 0)])
+def test_multi_workgroup_panel(M, orc, tuning, P, variant):
     """Small workgroups spread a 700-row panel over several workgroups (grid barrier), with
     and without the concurrent side-stream update."""
-    monkeypatch.setenv("MDLS_PANEL_CFG", cfg)
-    if True:
-        m, n, tile = 700, 64, 16
-        print("case multi-wg P=%d cfg=%s" % (P, cfg), flush=True)
-        A, xt = mdgen.ls_problem(P, m, n, 55)
-        b = orc.rhs_for(A, xt)
-        ref = orc.lstsq(A, b)
-        outs = []
-        for la in ("1", "0"):
-            monkeypatch.setenv("MDLS_LOOKAHEAD", la)
-            x, info = M.solve(P, to_gpu(A), to_gpu(b), tile)
-            torch.cuda.synchronize()
-            assert int(info.item()) == 0
-            assert md_err(x.cpu().numpy(), ref["x"]) <= TOL[P] * max(1, kappa(A))
-            outs.append(x.cpu().numpy())
-        assert np.array_equal(outs[0], outs[1])  # same arithmetic in the same order
+    from paper_2110_08375_amd import mdls
+
+    tuning(mdls.MDLS_TUNE_PANEL_VARIANT, variant)
+    m, n, tile = 700, 64, 16
+    print("case multi-wg P=%d variant=%d" % (P, variant), flush=True)
+    A, xt = mdgen.ls_problem(P, m, n, 55)
+    b = orc.rhs_for(A, xt)
+    ref = orc.lstsq(A, b)
+    outs = []
+    for la in (1, 0):
+        tuning(mdls.MDLS_TUNE_LOOKAHEAD, la)
+        x, info = M.solve(P, to_gpu(A), to_gpu(b), tile)
+        torch.cuda.synchronize()
+        assert int(info.item()) == 0
+        assert md_err(x.cpu().numpy(), ref["x"]) <= TOL[P] * max(1, kappa(A))
+        outs.append(x.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])  # same arithmetic in the same order
 
 
 @pytest.mark.parametrize("P", (2, 4, 8))
@@ -126,13 +150,18 @@ def test_qr_t_apply_qt_and_w(M, orc, P):
     qtb_ref = orc.apply_qt(Fo, beta, B)
     Ag = to_gpu(A)
     T = torch.zeros((P, n, tile), dtype=torch.float64, device=dev())
-    M.qr(P, Ag, tile, T=T)
+    bg = torch.full((P, n), 7.0, dtype=torch.float64, device=dev())
+    info = torch.full((1,), 5, dtype=torch.int32, device=dev())
+    M.qr(P, Ag, tile, T=T, beta=bg, info=info)
     Bg = to_gpu(B)
     M.apply_qt(P, Ag, T, Bg, tile)
     W = torch.zeros((P, n, m), dtype=torch.float64, device=dev())
     M.form_w(P, Ag, T, tile, W)
     torch.cuda.synchronize()
+    assert int(info.item()) == 0
     k = kappa(A)
+    # the betas against the oracle's
+    assert md_err(bg.cpu().numpy(), beta) <= TOL[P] * max(1, k)
     Bq = Bg.cpu().numpy()
     for c in range(3):
         assert md_err(Bq[:, c, :], qtb_ref[:, c, :]) <= TOL[P] * max(1, k)
@@ -217,21 +246,115 @@ def test_run_to_run_bitwise(M):
     assert np.array_equal(outs[0], outs[1])
 
 
-@pytest.mark.parametrize("P,m,n,tile", [(2, 1024, 1024, 128), (2, 2048, 1024, 128), (4, 1024, 1024, 128),
-                                        (4, 2048, 1024, 128), (8, 1024, 1024, 128), (8, 2048, 1024, 128)])
-def test_full_size_recovers_x_true(M, orc, P, m, n, tile):
-    """The n = 1024 headline sizes: b = A x_true formed exactly by the oracle and rounded to P
-    limbs, so the computed x must match x_true to the kappa-scaled tolerance."""
-    print("case full P=%d m=%d n=%d" % (P, m, n), flush=True)
+def md_diff_max(X, Y):
+    """max |X - Y| of two md arrays (limb axis first), the limb differences summed from the bottom"""
+    d = np.zeros(X.shape[1:])
+    for k in range(X.shape[0] - 1, -1, -1):
+        d = d + (X[k] - Y[k])
+    return float(np.max(np.abs(d)))
+
+
+# The headline workload (Section 4, Table 11: least squares on 1024 x 1024, 8 tiles of 128) in
+# dd and qd, its tall 2048 x 1024 variant in dd, and od at 768 x 768, the largest square size whose
+# oracle run fits the test budget and still reaches the full-size paths of the factorisation:
+# 256-row trailing-update units (at least 2 x 256 units in the first panels) and the od update's
+# switch from 448 to 224 workgroups below 768 rows.
+HEADLINE = [(2, 1024, 1024, 128), (4, 1024, 1024, 128), (2, 2048, 1024, 128), (8, 768, 768, 128)]
+
+
+@pytest.mark.parametrize("P,m,n,tile", HEADLINE)
+def test_full_size_matches_oracle(M, orc, P, m, n, tile):
+    """R, Q^T b, x and the Householder vectors of the full-size solve against the oracle's
+    unblocked solve of the same data, element by element, with the kappa-scaled contract and the tight bound 64 n u_P kappa;
+    x also against x_true (b = A x_true formed exactly by the oracle, rounded to P limbs)."""
+    print("case full-size oracle P=%d m=%d n=%d tile=%d" % (P, m, n, tile), flush=True)
     A, xt = mdgen.ls_problem(P, m, n, 2000 + P)
     b = orc.rhs_for(A, xt)
-    x, info = M.solve(P, to_gpu(A), to_gpu(b), tile)
+    ref = orc.lstsq(A, b)
+    print("  oracle done", flush=True)
+    Ag, bg = to_gpu(A), to_gpu(b)
+    x, info = M.solve(P, Ag, bg, tile)
     torch.cuda.synchronize()
     assert int(info.item()) == 0
     k = kappa(A)
-    err = md_err(x.cpu().numpy(), xt)
-    report("full", err, TOL[P] * max(1, k))
-    assert err <= TOL[P] * max(1.0, k)
+    u = unit(P)
+    tight = 64 * n * u * k
+    loose = TOL[P] * max(1.0, k)
+    xg = x.cpu().numpy()
+    ex = md_err(xg, ref["x"])
+    et = md_err(xg, xt)
+    Fg = Ag.cpu().numpy()
+    Rg = np.stack([np.triu(Fg[l].T[:n, :]) for l in range(P)])
+    Ro = np.stack([np.triu(ref["F"][l].T[:n, :]) for l in range(P)])
+    eR = md_diff_max(Rg, Ro) / float(np.max(np.abs(Ro[0])))
+    eq = md_err(bg.cpu().numpy(), ref["qtb"])
+    # the Householder vectors below the diagonal (unit first entries implicit)
+    Vg = np.stack([np.tril(Fg[l].T, -1) for l in range(P)])
+    Vo = np.stack([np.tril(ref["F"][l].T, -1) for l in range(P)])
+    ev = md_diff_max(Vg, Vo) / float(np.max(np.abs(Vo[0])))
+    print("  kappa %.3e; x vs oracle %.3e (%.2f u kappa), x vs x_true %.3e (%.2f u kappa), "
+          "R %.3e (%.2f u kappa), Q^T b %.3e (%.2f u kappa), v %.3e (%.2f u kappa); tight bound %.3e"
+          % (k, ex, ex / (u * k), et, et / (u * k), eR, eR / (u * k), eq, eq / (u * k), ev, ev / (u * k), tight),
+          flush=True)
+    for e in (ex, et, eR, eq, ev):
+        assert e <= loose
+        assert e <= tight
+
+
+@pytest.mark.parametrize("P", (2, 4, 8))
+def test_nan_input_propagates(M, P):
+    """A NaN in A comes out as NaN in x, every kernel exits, d_info stays 0 (NaN is not an
+    exact zero), and the next solve on the same stream is unaffected."""
+    m, n, tile = 300, 128, 32
+    A, xt = mdgen.ls_problem(P, m, n, 31)
+    b = mdgen.md_vector(P, m, 31, mdgen.STREAM_B)
+    An = A.copy()
+    An[0, 3, 5] = np.nan
+    x, info = M.solve(P, to_gpu(An), to_gpu(b), tile)
+    torch.cuda.synchronize()
+    assert int(info.item()) == 0
+    xh = x.cpu().numpy()
+    assert np.isnan(xh).any()
+    x2, info2 = M.solve(P, to_gpu(A), to_gpu(b), tile)
+    torch.cuda.synchronize()
+    assert int(info2.item()) == 0
+    assert np.isfinite(x2.cpu().numpy()).all()
+    # back substitution with a NaN in R
+    R = mdgen.upper_triangular(P, n, 5, well_conditioned=True)
+    R[0, 70, 20] = np.nan
+    y = to_gpu(mdgen.md_vector(P, n, 5, mdgen.STREAM_B))
+    y, info3 = M.backsub(P, to_gpu(R), y, tile)
+    torch.cuda.synchronize()
+    assert int(info3.item()) == 0
+    assert np.isnan(y.cpu().numpy()).any()
+
+
+@pytest.mark.parametrize("P", (2, 8))
+def test_barrier_timeout_reports_minus_one(M, orc, tuning, P):
+    """With a spin limit of zero polls the panel's grid barriers give up at once: every kernel
+    still exits, the solve and the QR report d_info = -1.  With the limit restored the same
+    problem solves normally."""
+    from paper_2110_08375_amd import mdls
+
+    m, n, tile = 700, 64, 16  # 11 (dd) / 11 (od) panel workgroups
+    A, xt = mdgen.ls_problem(P, m, n, 57)
+    b = orc.rhs_for(A, xt)
+    tuning(mdls.MDLS_TUNE_SPIN_LIMIT, 0)
+    x, info = M.solve(P, to_gpu(A), to_gpu(b), tile)
+    torch.cuda.synchronize()
+    assert int(info.item()) == -1
+    qinfo = torch.full((1,), 9, dtype=torch.int32, device=dev())
+    M.qr(P, to_gpu(A), tile, info=qinfo)
+    torch.cuda.synchronize()
+    assert int(qinfo.item()) == -1
+    tuning(mdls.MDLS_TUNE_SPIN_LIMIT, 1 << 22)
+    x, info = M.solve(P, to_gpu(A), to_gpu(b), tile)
+    torch.cuda.synchronize()
+    assert int(info.item()) == 0
+    assert md_err(x.cpu().numpy(), xt) <= TOL[P] * max(1.0, kappa(A))
+    M.qr(P, to_gpu(A), tile, info=qinfo)
+    torch.cuda.synchronize()
+    assert int(qinfo.item()) == 0
 
 
 def test_backsub_full_size_exact_rhs(M):

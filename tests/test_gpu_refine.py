@@ -1,7 +1,10 @@
 """GPU parity of the refined least-squares form (double-double factorisation, refinement with
-quad- or octo-double residuals) through the C ABI, on kappa = 1e8 matrices (U diag(s) V^T) with
-consistent right-hand sides b = A x_true formed exactly by the oracle and rounded to the target
-precision: x must match x_true to TOL[P] * kappa, like the plain solver at that precision."""
+quad- or octo-double residuals) through the C ABI, on kappa = 1e8 matrices (U diag(s) V^T):
+with consistent right-hand sides b = A x_true formed exactly by the oracle and rounded to the
+target precision, x must match x_true to TOL[P] * kappa, like the plain solver at that
+precision; with an inconsistent b (a residual orthogonal to range(A)), x must match the
+oracle's least-squares solution of the stored data at the target precision, to
+TOL[P] kappa (1 + kappa rho), rho = ||r|| / (||A|| ||x||) (the least-squares perturbation bound)."""
 import numpy as np
 import pytest
 
@@ -23,6 +26,8 @@ def M():
     import paper_2110_08375_amd as M
 
     M.lib()
+    torch.zeros(1, device=dev())
+    M.init()
     return M
 
 
@@ -37,8 +42,18 @@ def md_err(x, ref):
     return np.max(np.abs(d)) / max(np.max(np.abs(ref[0])), 1e-300)
 
 
-@pytest.mark.parametrize("P,m,n,tile,iters", [(4, 256, 256, 64, 4), (8, 256, 256, 64, 6), (8, 300, 128, 32, 6)])
+def steps_taken(norms):
+    nr = norms.cpu().numpy().reshape(-1, 2)
+    taken = nr[:, 0] >= 0
+    k = int(np.argmin(taken)) if not taken.all() else len(taken)
+    assert taken[:k].all() and not taken[k:].any()  # steps not taken are marked -1 at the end
+    return nr[:k]
+
+
+@pytest.mark.parametrize("P,m,n,tile,iters", [(4, 256, 256, 64, 8), (8, 256, 256, 64, 10), (8, 300, 128, 32, 10)])
 def test_refined_recovers_x_true(M, orc, P, m, n, tile, iters):
+    """Consistent b: x_true to the target tolerance, and the refinement stops by itself on its
+    correction norms before the step limit."""
     print("case refined P=%d m=%d n=%d" % (P, m, n), flush=True)
     A = mdgen.conditioned(2, m, n, 40 + n, kappa=1e8)
     xt = mdgen.md_vector(P, n, 41, mdgen.STREAM_X)
@@ -48,11 +63,49 @@ def test_refined_recovers_x_true(M, orc, P, m, n, tile, iters):
     assert int(info.item()) == 0
     kap = float(np.linalg.cond(A[0].T))
     err = md_err(x.cpu().numpy(), xt)
-    nr = norms.cpu().numpy().reshape(-1, 2)
-    print("refined P=%d err %.3e kappa %.3e corrections %s" % (P, err, kap, nr[:, 0] / nr[:, 1]), flush=True)
-    assert err <= TOL[P] * max(1.0, kap)
+    nr = steps_taken(norms)
     rel = nr[:, 0] / nr[:, 1]
+    print("refined P=%d err %.3e kappa %.3e steps %d corrections %s" % (P, err, kap, len(nr), rel), flush=True)
+    assert err <= TOL[P] * max(1.0, kap)
+    assert 3 <= len(nr) < iters  # stopped on the norms, not on the limit
     assert rel[1] < 1e-12 * rel[0] and rel[2] < rel[1]  # the corrections shrink geometrically
+    # the stopping rule: the last step's correction, or its contraction estimate, is below u
+    u = 2.0 ** -(53 * P - (P - 1))
+    assert rel[-1] <= u or rel[-1] * (nr[-1, 0] / nr[-2, 0]) <= u
+
+
+@pytest.mark.parametrize("P,m,n,tile", [(4, 512, 256, 64), (8, 512, 256, 64)])
+def test_refined_inconsistent_matches_oracle(M, orc, P, m, n, tile):
+    """Tall kappa = 1e8 system with a nonzero residual: b = A x_true + t r, r orthogonal to
+    range(A) (from the FP64 least-squares residual of a random vector), formed exactly by the
+    oracle at the target precision.  The refined x against the oracle's least-squares solution of
+    the same (A promoted to P limbs, b) data."""
+    print("case refined inconsistent P=%d m=%d n=%d" % (P, m, n), flush=True)
+    A = mdgen.conditioned(2, m, n, 90 + P, kappa=1e8)
+    xt = mdgen.md_vector(P, n, 91, mdgen.STREAM_X)
+    A64 = A[0].T + A[1].T
+    g = mdgen.md_vector(1, m, 92, mdgen.STREAM_B)[0]
+    r = g - A64 @ np.linalg.lstsq(A64, g, rcond=None)[0]
+    t = 1e-6 / np.linalg.norm(r)
+    rv = np.zeros((P, m))
+    rv[0] = t * r
+    b = -orc.matvec(A, xt, P, c=-rv)  # c - A x with c = -t r, negated (exact)
+    Ap = np.zeros((P, n, m))
+    Ap[:2] = A
+    ref = orc.lstsq(Ap, b)
+    x, info, norms = M.solve_refined(P, to_gpu(A), to_gpu(b), tile, 12)
+    torch.cuda.synchronize()
+    assert int(info.item()) == 0
+    kap = float(np.linalg.cond(A64))
+    xo = ref["x"]
+    rho = np.linalg.norm(t * r) / (np.linalg.norm(A64, 2) * np.linalg.norm(xo[0]))
+    err = md_err(x.cpu().numpy(), xo)
+    nr = steps_taken(norms)
+    bound = TOL[P] * kap * (1.0 + kap * rho)
+    print("refined inconsistent P=%d err vs oracle %.3e bound %.3e kappa %.3e rho %.3e steps %d"
+          % (P, err, bound, kap, rho, len(nr)), flush=True)
+    assert err <= bound
+    assert len(nr) < 12
 
 
 @pytest.mark.parametrize("P,iters", [(4, 4), (8, 6)])

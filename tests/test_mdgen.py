@@ -81,3 +81,19 @@ def test_conditioned_matrix_has_requested_kappa():
     s = np.linalg.svd(A[0].T, compute_uv=False)
     assert abs(s[0] - 1.0) < 1e-9 and abs(s[-1] / 1e-6 - 1.0) < 1e-6
     assert np.all(np.abs(A[1]) <= np.spacing(np.abs(A[0])))
+
+
+def test_conditioned_exact_rhs_is_exact():
+    """b = A x_true of the exact-rhs precision-form input, checked in exact rationals; kappa
+    stays at the requested 1e8 after the rounding of A."""
+    from fractions import Fraction
+
+    m, n = 96, 64
+    A, x, b = mdgen.conditioned_exact(4, m, n, 5)
+    assert np.all(A[1:] == 0) and np.all(x[1:] == 0) and np.all(b[2:] == 0)
+    for i in range(m):
+        S = sum(Fraction(float(A[0, j, i])) * Fraction(float(x[0, j])) for j in range(n))
+        assert S == Fraction(float(b[0, i])) + Fraction(float(b[1, i])), i
+        assert abs(b[1, i]) <= abs(np.spacing(b[0, i]))  # two non-overlapping limbs
+    k = np.linalg.cond(A[0].T)
+    assert 0.9e8 < k < 1.1e8
