@@ -200,15 +200,17 @@ __device__ __forceinline__ int slot_scatter_index(int lane)
 // the look-ahead: the rest of the trailing matrix is updated by the k_apply_s/t/u kernels
 // concurrently).
 //
-// Column j of the panel, x = A(j:h, j) with x1 = a_jj, sigma = sum_{i>j} x_i^2, mu = ||x||:
-// the Householder vector is kept unnormalised as u = gamma (x - mu e1), with
-//   x1 <= 0: gamma = 1,        u1 = x1 - mu, tau = -1/(mu u1),
-//   x1 >  0: gamma = x1 + mu,  u1 = -sigma,  tau = 1/(mu sigma gamma),
-// (both without cancellation, Golub-Van Loan 5.1.1), so that H = I - tau u u^T and the
-// per-column chain needs one square root and one reciprocal.  For c > j, with d_c =
-// sum_{i>j} x_i a_ic from the same reduction as sigma, t_c = u1 a_jc + gamma d_c and the
-// update is a_ic -= tau gamma t_c x_i (i > j), a_jc -= tau u1 t_c.  The stored x becomes
-// v = u / u1 (scale rho = gamma/u1), beta = tau u1^2, and column j of T follows from
+// Column j of the panel, x = A(j:h, j) with x1 = a_jj, sigma = sum_{i>j} x_i^2, q = x1^2 + sigma,
+// mu = sqrt(q): the Householder vector of Golub-Van Loan 5.1.1 is v = x rho below the
+// diagonal with v_j = 1, where rho = 1/v1 and v1 = x1 - mu (x1 <= 0) or -sigma/(x1 + mu)
+// (x1 > 0), so rho = -1/(mu - x1) = -(mu + x1)/sigma in both cases; beta = 2/(v^T v) and
+// beta rho = -1/mu, so beta = 1 - x1/mu.  For c > j, with d_c = sum_{i>j} x_i a_ic from the
+// same reduction as sigma, w_c = v^T a_c = a_jc + rho d_c and the update is
+// a_ic += (w_c/mu) x_i (i > j), a_jc -= beta w_c.  The per-column chain is the square root;
+// the reciprocals 1/q and 1/sigma are formed beside it in other waves, and then
+// 1/mu = mu (1/q), rho = -(mu + x1) (1/sigma) cost one product each.  Where these forms
+// cancel (sigma < x1^2: mu + x1 for x1 < 0, 1 - x1/mu for x1 > 0) rho = -1/(mu - x1) and
+// beta = -(1/mu)/rho are used instead.  Column j of T follows from
 // T(0:j, j) = -beta_j T(0:j, 0:j) (Y(:, 0:j)^T v_j) (Schreiber and Van Loan's compact WY).
 template <int P, int W, int R, int NT>
 __device__ __forceinline__ void panel_run(const PanelArgs &g, int bid)
@@ -223,16 +225,16 @@ __device__ __forceinline__ void panel_run(const PanelArgs &g, int bid)
     __shared__ double s_tot[W * P];       // column j's reduction: sigma (l = j), d_l, Gram sums
     __shared__ double s_hd[W * P];        // row j: a_jl
     __shared__ double s_mu[P];
-    __shared__ double s_tau[P];
-    __shared__ double s_ec[W * P];        // gamma t_c
-    __shared__ double s_fc[W * W * P];    // [j][c]: u1 t_c of column j (deferred row-j update)
-    __shared__ double s_info[W * 2 * P];  // per column: u1, tau
+    __shared__ double s_iq[P];            // 1/q
+    __shared__ double s_is[P];            // 1/sigma
+    __shared__ double s_fc[W * W * P];    // [j][c]: w_c = v_j^T a_c (deferred row-j update)
+    __shared__ double s_info[W * 2 * P];  // per column: 1/mu, x1
     __shared__ double s_gram[W * W * P];  // [j][l]: sum_{i>j} x_j(i) x_l(i), l < j
     __shared__ double s_hrow[W * W * P];  // [j][l]: a_jl when column j is processed, l < j
     __shared__ double s_rho[W * P];
     __shared__ double s_beta[W * P];
     __shared__ double s_T[W * W * P];     // T, column-major
-    __shared__ int s_flag[W];             // sigma == 0
+    __shared__ int s_flag[W];             // per column: 1 sigma == 0, 2 beta from rho (x1 > 0, sigma < x1^2)
 
     // The panel is the critical path of the factorisation: its waves take issue priority over
     // the trailing-update waves that may share their compute unit.
@@ -247,12 +249,15 @@ __device__ __forceinline__ void panel_run(const PanelArgs &g, int bid)
     unsigned nbar = 0;
 
     // Off-chain pieces of the compact-WY factor (block 0; beta and T are written by it only).
-    // beta_jj = tau u1^2 (wave 2)
+    // beta_jj = 1 - x1/mu, or -(1/mu)/rho where that form cancels (wave 2)
     auto t_beta = [&](int jj) __attribute__((always_inline)) {
         V<P> beta = zero<P>();
-        if (!s_flag[jj]) {
-            const V<P> u1 = lds_ld<P>(&s_info[(jj * 2 + 0) * P]);
-            beta = mul(lds_ld<P>(&s_info[(jj * 2 + 1) * P]), mul(u1, u1));
+        if (!(s_flag[jj] & 1)) {
+            const V<P> r = lds_ld<P>(&s_info[(jj * 2 + 0) * P]);
+            if (s_flag[jj] & 2)
+                beta = neg(mul(r, recip(lds_ld<P>(&s_rho[jj * P]))));
+            else
+                beta = fma(from_double<P>(1.0), neg(lds_ld<P>(&s_info[(jj * 2 + 1) * P])), r);
         }
         if (lane == 0) {
             lds_st(&s_beta[jj * P], beta);
@@ -285,7 +290,7 @@ __device__ __forceinline__ void panel_run(const PanelArgs &g, int bid)
         const V<P> bj = lds_ld<P>(&s_beta[jj * P]);
         if (lane < W) {
             V<P> t = zero<P>();
-            if (lane < jj && !s_flag[jj]) t = neg(mul(bj, w));
+            if (lane < jj && !(s_flag[jj] & 1)) t = neg(mul(bj, w));
             if (lane == jj) t = bj;
             lds_st(&s_T[(jj * W + lane) * P], t);
             stm(g.T, g.tps, (long)jj * W + lane, t);
@@ -394,20 +399,19 @@ __device__ __forceinline__ void panel_run(const PanelArgs &g, int bid)
         __syncthreads();
     }
 
-    // Per column j the serial chain (reduction, mu, tau) runs in wave 0; the other waves do
-    // the off-chain work between the same workgroup barriers:
+    // Per column j the serial chain (reduction, mu, 1/mu, w_c) runs through waves 0 and 1; the
+    // other waves do the off-chain work between the same workgroup barriers:
     //   [B1, B2]  wave 0: reduction of the partial sums (and the grid exchange);
     //             wave 2: beta of column j-1; wave 3: g(l, j-1) (block 0 only), and for
     //             P <= 4 also w = T(:, :j-1) g(:, j-1), which is longer than mu there
-    //   [B2, M]   wave 0: mu; wave 1: A_c; wave 2: 1/sigma; wave 3 (P = 8): w
-    //   [M, Tb]   wave 0: tau; wave 1: e_c = gamma t_c, f_c = u1 t_c with t_c = A_c + mu B_c;
-    //             wave 2: rho_j; wave 3: T(:, j-1) = -beta w
-    //   after Tb  every thread: coef_c = tau e_c and the update of its rows below row j.
-    // Row j of the columns c > j (a_jc -= tau f_c) is not needed again inside the panel, so
+    //   [B2, M]   wave 0: mu = sqrt(q); wave 1: 1/q; wave 2: 1/sigma; wave 3 (P = 8): w
+    //   [M, Tb]   wave 0: 1/mu = mu (1/q); wave 1: rho_j and w_c = a_jc + rho_j d_c;
+    //             wave 3: T(:, j-1) = -beta w
+    //   after Tb  every thread: coef_c = w_c / mu and the update of its rows below row j.
+    // Row j of the columns c > j (a_jc -= beta w_c) is not needed again inside the panel, so
     // that update waits for the end of the panel.
-    // values a wave carries across barriers, by role: wave 0 x1^2 + sigma; wave 1 A_c, B_c;
-    // wave 2 1/sigma; wave 3 g, then w
-    V<P> cx = zero<P>(), cy = zero<P>();
+    // wave 3 carries g, then w, across barriers
+    V<P> cx = zero<P>();
     // where w is formed: beside the reduction while the md scalars are cheap (P <= 4); beside mu
     // for od, whose reduction window is the shorter one in late panels
     constexpr bool kEarlyW = P <= 4;
@@ -503,61 +507,40 @@ __device__ __forceinline__ void panel_run(const PanelArgs &g, int bid)
         const V<P> x1 = lds_ld<P>(&s_hd[j * P]);
         const bool zs = is_zero(sig);
         const bool pos = x1.x[0] > 0.0;
+        const bool small = sig.x[0] < x1.x[0] * x1.x[0];  // sigma < x1^2: the cancelling forms are avoided
         if (wid == 0) {
             if (!zs) {
-                cx = fma(sig, x1, x1);
-                const V<P> mu = sqrt_md(cx);
+                const V<P> mu = sqrt_md(fma(sig, x1, x1));
                 if (lane == 0) lds_st(s_mu, mu);
             }
-            if (lane == 0) s_flag[j] = zs ? 1 : 0;
+            if (lane == 0) s_flag[j] = zs ? 1 : ((pos && small) ? 2 : 0);
         } else if (wid == 1) {
-            if (!zs && lane > j && lane < W) {
-                const V<P> d = lds_ld<P>(&s_tot[lane * P]), ajc = lds_ld<P>(&s_hd[lane * P]);
-                if (pos) {  // t_c = (x1 d_c - sigma a_jc) + mu d_c
-                    Acc<P> t = acc_zero<P>();
-                    acc_fma(t, x1, d);
-                    acc_fma(t, neg(sig), ajc);
-                    cx = acc_get(t);
-                    cy = d;
-                } else {  // t_c = (d_c + x1 a_jc) - mu a_jc
-                    cx = fma(d, x1, ajc);
-                    cy = neg(ajc);
-                }
+            if (!zs) {
+                const V<P> iq = recip(fma(sig, x1, x1));
+                if (lane == 0) lds_st(s_iq, iq);
             }
         } else if (wid == 2) {
-            if (!zs && pos) cx = recip(sig);
+            if (!zs && (pos || !small)) {
+                const V<P> is = recip(sig);
+                if (lane == 0) lds_st(s_is, is);
+            }
         } else if (wid == 3 && bid == 0 && j > 0) {
             if constexpr (!kEarlyW) cx = t_w(j - 1, cx);
         }
         __syncthreads();  // M
         if (wid == 0) {
-            if (!zs) {
-                // tau = 1/(mu (mu - x1)) for x1 <= 0, 1/(mu sigma (x1 + mu)) for x1 > 0; with
-                // E = x1^2 + sigma + mu |x1| both denominators are E or sigma E
-                const V<P> mu = lds_ld<P>(s_mu);
-                const V<P> e = fma(cx, mu, pos ? x1 : neg(x1));
-                const V<P> tau = recip(pos ? mul(sig, e) : e);
-                if (lane == 0) {
-                    lds_st(s_tau, tau);
-                    lds_st(&s_info[(j * 2 + 1) * P], tau);
-                }
+            if (!zs && lane == 0) {
+                lds_st(&s_info[(j * 2 + 0) * P], mul(lds_ld<P>(s_mu), lds_ld<P>(s_iq)));  // 1/mu
+                lds_st(&s_info[(j * 2 + 1) * P], x1);
             }
         } else if (wid == 1) {
-            if (!zs) {
-                const V<P> mu = lds_ld<P>(s_mu);
-                if (lane > j && lane < W) {
-                    const V<P> t = fma(cx, mu, cy);
-                    lds_st(&s_ec[lane * P], pos ? mul(t, add(x1, mu)) : t);
-                    lds_st(&s_fc[(j * W + lane) * P], mul(t, pos ? neg(sig) : sub(x1, mu)));
-                }
-                if (lane == 0) lds_st(&s_info[(j * 2 + 0) * P], pos ? neg(sig) : sub(x1, mu));
-            }
-        } else if (wid == 2) {
-            // rho_j = gamma / u1: -1/(mu - x1) for x1 <= 0, -(x1 + mu)/sigma for x1 > 0
+            // rho = 1/v1, then w_c = a_jc + rho d_c for the columns right of j
             V<P> rho = from_double<P>(1.0);
             if (!zs) {
                 const V<P> mu = lds_ld<P>(s_mu);
-                rho = pos ? neg(mul(add(x1, mu), cx)) : neg(recip(sub(mu, x1)));
+                rho = (!pos && small) ? neg(recip(sub(mu, x1))) : neg(mul(add(mu, x1), lds_ld<P>(s_is)));
+                if (lane > j && lane < W)
+                    lds_st(&s_fc[(j * W + lane) * P], fma(lds_ld<P>(&s_hd[lane * P]), lds_ld<P>(&s_tot[lane * P]), rho));
             }
             if (lane == 0) lds_st(&s_rho[j * P], rho);
         } else if (wid == 3 && bid == 0 && j > 0) {
@@ -567,8 +550,8 @@ __device__ __forceinline__ void panel_run(const PanelArgs &g, int bid)
         // ---- 3. reflector j applied to the columns c > j below row j; mu on the diagonal
         if (!zs) {
             const V<P> mu = lds_ld<P>(s_mu);
-            V<P> ncoef = zero<P>();
-            if (c > j) ncoef = neg(mul(lds_ld<P>(s_tau), lds_ld<P>(&s_ec[c * P])));
+            V<P> coef = zero<P>();  // w_c / mu
+            if (c > j) coef = mul(lds_ld<P>(&s_fc[(j * W + c) * P]), lds_ld<P>(&s_info[(j * 2 + 0) * P]));
 #pragma unroll
             for (int k = 0; k < R; ++k) {
                 const long r = rbase + k * rstride;
@@ -576,7 +559,7 @@ __device__ __forceinline__ void panel_run(const PanelArgs &g, int bid)
                 if (r == dj) {
                     if (c == j) a[k] = mu;
                 } else if (r > dj && r < hh && c > j) {
-                    a[k] = fma(a[k], ncoef, xk);
+                    a[k] = fma(a[k], coef, xk);
                 }
             }
         }
@@ -595,9 +578,9 @@ __device__ __forceinline__ void panel_run(const PanelArgs &g, int bid)
         if (r < hh && c < g.wact) {
             const long jr = r - off;  // panel row
             if (jr >= 0 && jr < c) {
-                if (!s_flag[jr])
-                    a[k] = sub(a[k], mul(lds_ld<P>(&s_info[(jr * 2 + 1) * P]), lds_ld<P>(&s_fc[(jr * W + c) * P])));
-            } else if (jr > c && !s_flag[c]) {
+                if (!(s_flag[jr] & 1))
+                    a[k] = fma(a[k], neg(lds_ld<P>(&s_beta[jr * P])), lds_ld<P>(&s_fc[(jr * W + c) * P]));
+            } else if (jr > c && !(s_flag[c] & 1)) {
                 a[k] = mul(a[k], rc);
             }
             stm(g.A, g.ps, c * g.lda + r, a[k]);
