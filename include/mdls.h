@@ -309,19 +309,22 @@ typedef struct {
  * Refined least squares (the precision form): the accuracy of p_out = 4 (qd) or 8 (od) limbs
  * from a double-double factorisation.  A (m x n, double double, ld lda, read only) is copied
  * into F (same shape and ld, overwritten by its dd factors); Householder QR of F in dd with
- * the tile T factors (Section 3); then iters refinement steps, each: r := b - A x formed in
- * p_out limbs (x = 0 in the first), d := R^-1 (Q^T r)(0:n) in dd (r rounded to dd; Q^T by the
- * tile reflectors, R^-1 by the tiled back substitution of Section 2), x += d in p_out limbs.
+ * the tile T factors (Section 3); then at most iters refinement steps with the residuals in
+ * p_out limbs and the corrections in dd (Q^T and Q by the tile reflectors, R^-1 and R^-T by the
+ * tiled back substitution of Section 2 and its transpose, with the tile inverses formed once):
+ *   m == n: r := b - A x (x = 0 in the first step), d := R^-1 (Q^T r)(0:n), x += d;
+ *   m > n: refinement of the augmented system [I A; A^T 0][r; x] = [b; 0] (Bjorck 1967), so
+ *   that a nonzero residual does not limit the accuracy: r and x start at 0, and each step
+ *   forms f := b - r - A x and g := -A^T r, then h := R^-T g, d := Q^T f,
+ *   x += R^-1 (d(0:n) - h) and r += Q [h; d(n:m)].
  * b: P = p_out planes of m; x: p_out planes of n (output).  Each step gains about
- * -log10(kappa(A) 2^-105) digits while kappa(A) 2^-105 << 1 (for an inconsistent b the
- * contraction also grows with kappa(A)^2 times the relative residual).  iters is the most
+ * -log10(kappa(A) 2^-105) digits while kappa(A) 2^-105 << 1.  iters is the most
  * steps taken: the call stops on the device once the correction norms show convergence, when
  * max|d| <= u max|x| or when the next correction estimated from the observed contraction,
  * d_k^2 / d_(k-1), is below u max|x| (u = 2^-(53 p_out - p_out + 1)); later steps' kernels then
- * return at once, so the call stays asynchronous and capturable.  The tile inverses of R are
- * formed once.  d_norms (2 iters device doubles) receives max |d| and max |x| (leading limbs)
- * of each step taken and -1, -1 for steps not taken.  *d_info as for mdls_solve.
- * n % tile == 0.
+ * return at once, so the call stays asynchronous and capturable.  d_norms (2 iters device
+ * doubles) receives max |d| and max |x| (leading limbs) of each step taken and -1, -1 for
+ * steps not taken.  *d_info as for mdls_solve.  n % tile == 0.
  *   mdls_refined_workspace_bytes(p_out, m, n, tile)   workspace (0 if arguments invalid).
  */
 size_t mdls_refined_workspace_bytes(int p_out, int m, int n, int tile);

@@ -1061,15 +1061,17 @@ __global__ __launch_bounds__(kThreads) void k_resid_part(const double *A, long l
     for (int k = 0; k < PX; ++k) part[((long)blockIdx.y * PX + k) * m + i] = acc.s[k];
 }
 
-// r_i = b_i - sum_ch part[ch][.][i] (chunks in order)
+// r_i = b_i - c_i - sum_ch part[ch][.][i] (chunks in order; c, PX limbs, may be null)
 template <int PX>
-__global__ __launch_bounds__(kThreads) void k_resid_fin(const double *b, long bps, const double *part, int m, int nch,
-                                                        double *r, long rps, const int *skip)
+__global__ __launch_bounds__(kThreads) void k_resid_fin(const double *b, long bps, const double *c, long cps,
+                                                        const double *part, int m, int nch, double *r, long rps,
+                                                        const int *skip)
 {
     if (*skip) return;
     const long i = (long)blockIdx.x * kThreads + threadIdx.x;
     if (i >= m) return;
     Acc<PX> t = acc_from(ldm<PX>(b, bps, i));
+    if (c) acc_add(t, neg(ldm<PX>(c, cps, i)));
     for (int ch = 0; ch < nch; ++ch) {
         V<PX> o;
 #pragma unroll
@@ -1077,6 +1079,52 @@ __global__ __launch_bounds__(kThreads) void k_resid_fin(const double *b, long bp
         acc_add(t, o);
     }
     stm(r, rps, i, acc_get(t));
+}
+
+// g_i = -sum_k A_ki r_k (A of PA limbs, r of PX limbs, formed in PX limbs), rounded to PG <= PX
+// limbs: one wave per column of A, the lanes walk its rows
+template <int PA, int PX, int PG>
+__global__ __launch_bounds__(kThreads) void k_resid_t(const double *A, long lda, long psa, int m, int n,
+                                                      const double *r, long rps, double *g, long gps, const int *skip)
+{
+    if (*skip) return;
+    const int lane = threadIdx.x & 63;
+    const int col = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (col >= n) return;
+    Acc<PX> acc = acc_zero<PX>();
+    int nt = 0;
+    for (int i = lane; i < m; i += 64) {
+        const V<PA> a = ldm<PA>(A, psa, (long)col * lda + i);
+        const V<PX> rv = ldm<PX>(r, rps, i);
+        casc_fma<PX, PA, PX, 0, 0, true>(acc.s, a.x, rv.x, nullptr);
+        if (((++nt) % kLazy<PX>) == 0) acc = acc_from(acc_get(acc));
+    }
+    const V<PX> t = wave_sum(acc_get(acc));
+    if (lane == 0) stm(g, gps, col, resize<PG>(neg(t)));
+}
+
+// i < n: y_i = d_i - h_i, then d_i = h_i (d of length >= n; all P limbs)
+template <int P>
+__global__ __launch_bounds__(kThreads) void k_aug_split(double *d, long dps, const double *h, long hps, double *y,
+                                                        long yps, int n, const int *skip)
+{
+    if (*skip) return;
+    const long i = (long)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n) return;
+    const V<P> hv = ldm<P>(h, hps, i);
+    stm(y, yps, i, sub(ldm<P>(d, dps, i), hv));
+    stm(d, dps, i, hv);
+}
+
+// x_i += d_i (d of PD <= PX limbs), i < n
+template <int PX, int PD>
+__global__ __launch_bounds__(kThreads) void k_md_add(double *x, long xps, const double *d, long dps, int n,
+                                                     const int *skip)
+{
+    if (*skip) return;
+    const long i = (long)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n) return;
+    stm(x, xps, i, add(ldm<PX>(x, xps, i), resize<PX>(ldm<PD>(d, dps, i))));
 }
 
 // x_i += d_i (d of PD <= PX limbs); norms[0] = max |d_i|, norms[1] = max |x_i| (leading limbs;
@@ -1284,6 +1332,40 @@ __global__ __launch_bounds__(kThreads) void k_bs_xi(const double *Xi, long ldx, 
     if (lane == 0) stm(x, xps, row, s);
 }
 
+// The transposed sweep (forward substitution with R^T, whose diagonal tiles have the inverses
+// Xinv_i^T): h_i := Xinv_i^T g_i, one wave per output row; skipped while *skip is set
+template <int P>
+__global__ __launch_bounds__(kThreads) void k_bs_xi_t(const double *Xi, long ldx, long psx, const double *g, long gps,
+                                                     double *h, long hps, int tile, const int *skip)
+{
+    if (skip && *skip) return;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int row = blockIdx.x * 4 + wid;
+    if (row >= tile) return;
+    Acc<P> acc = acc_zero<P>();
+    int nt = 0;
+    for (int c = lane; c <= row; c += 64) acc_fma_step(acc, ldm<P>(Xi, psx, (long)row * ldx + c), ldm<P>(g, gps, c), nt++);
+    const V<P> s = wave_sum(acc_get(acc));
+    if (lane == 0) stm(h, hps, row, s);
+}
+
+// g(col) -= sum_k R(k, col) h_k over the tile's rows k, for the ncols columns right of the tile
+// (R points at the tile's first row and the first of those columns); one wave per column
+template <int P>
+__global__ __launch_bounds__(kThreads) void k_bs_upd_t(const double *R, long ldr, long psr, const double *h, long hps,
+                                                      double *g, long gps, int ncols, int tile, const int *skip)
+{
+    if (skip && *skip) return;
+    const int lane = threadIdx.x & 63;
+    const int col = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (col >= ncols) return;
+    Acc<P> acc = acc_zero<P>();
+    int nt = 0;
+    for (int k = lane; k < tile; k += 64) acc_fma_step(acc, ldm<P>(R, psr, (long)col * ldr + k), ldm<P>(h, hps, k), nt++);
+    const V<P> s = wave_sum(acc_get(acc));
+    if (lane == 0) stm(g, gps, col, sub(ldm<P>(g, gps, col), s));
+}
+
 // y(0:rows) -= R(0:rows, cols of tile i) x_i ; 64 rows per workgroup, the tile's columns
 // split over the 4 waves and combined in a fixed order
 template <int P>
@@ -1409,8 +1491,9 @@ __global__ __launch_bounds__(kThreads) void k_trmm_t(const double *T, long ldt, 
 // U(i, c) = sum_{l>=i} T(i, l) S(l, c) (T upper triangular, applied without transposition)
 template <int P>
 __global__ __launch_bounds__(kThreads) void k_trmm_n(const double *T, long ldt, long tps, const double *S, long sps,
-                                                    double *U, int tile, int nrhs)
+                                                    double *U, int tile, int nrhs, const int *skip)
 {
+    if (skip && *skip) return;
     const int i = blockIdx.x * kThreads + threadIdx.x, c = blockIdx.y;
     if (i >= tile || c >= nrhs) return;
     Acc<P> acc = acc_zero<P>();
@@ -1911,14 +1994,12 @@ int apply_qt_t(int m, int n, int tile, const double *A, int lda, const double *T
 
 // B := Q B = Q_0 Q_1 ... Q_{N-1} B with Q_k = I - Y_k T_k Y_k^T: the tiles in reverse order,
 // B -= Y_k T_k (Y_k^T B) (the paper forms Q itself, Algorithm 2; with B = I this is that Q).
+// S and U are scratch of P tile 64 doubles each; every kernel returns at once while *skip is set.
 template <int P>
-int apply_q_t(int m, int n, int tile, const double *A, int lda, const double *T, int ldt, double *B, int ldb, int nrhs,
-              void *ws, hipStream_t s)
+void apply_q_blocks(int m, int n, int tile, const double *A, int lda, const double *T, int ldt, double *B, int ldb,
+                    int nrhs, double *S, double *U, const int *skip, hipStream_t s)
 {
-    Ctx<P> cx{(char *)ws, layout(P, m, n, tile), s};
     const long psa = (long)lda * n, tps = (long)ldt * n, bps = (long)ldb * nrhs;
-    double *S = cx.big();
-    double *U = S + (size_t)P * tile * 64;
     const long sps = (long)tile * 64;
     const int N = n / tile;
     for (int c0 = 0; c0 < nrhs; c0 += 64) {
@@ -1929,13 +2010,22 @@ int apply_q_t(int m, int n, int tile, const double *A, int lda, const double *T,
             const double *Y = A + kt * lda + kt;
             const int h = m - (int)kt;
             MDLS_LAUNCH("k_tn", P, (double)h * tile * nc, (k_tn<P>), dim3((tile + 3) / 4, nc), dim3(kThreads), s, Y,
-                        (long)lda, psa, h, tile, Bc + kt, (long)ldb, bps, nc, S, sps, nullptr);
+                        (long)lda, psa, h, tile, Bc + kt, (long)ldb, bps, nc, S, sps, skip);
             MDLS_LAUNCH("k_trmm_n", P, 0.5 * tile * tile * nc, (k_trmm_n<P>), dim3((tile + kThreads - 1) / kThreads, nc),
-                        dim3(kThreads), s, T + kt * ldt, (long)ldt, tps, S, sps, U, tile, nc);
+                        dim3(kThreads), s, T + kt * ldt, (long)ldt, tps, S, sps, U, tile, nc, skip);
             MDLS_LAUNCH("k_nn_sub", P, (double)h * tile * nc, (k_nn_sub<P>), dim3((h + kThreads - 1) / kThreads, nc),
-                        dim3(kThreads), s, Y, (long)lda, psa, h, tile, U, sps, Bc + kt, (long)ldb, bps, nullptr);
+                        dim3(kThreads), s, Y, (long)lda, psa, h, tile, U, sps, Bc + kt, (long)ldb, bps, skip);
         }
     }
+}
+
+template <int P>
+int apply_q_t(int m, int n, int tile, const double *A, int lda, const double *T, int ldt, double *B, int ldb, int nrhs,
+              void *ws, hipStream_t s)
+{
+    Ctx<P> cx{(char *)ws, layout(P, m, n, tile), s};
+    double *S = cx.big();
+    apply_q_blocks<P>(m, n, tile, A, lda, T, ldt, B, ldb, nrhs, S, S + (size_t)P * tile * 64, nullptr, s);
     return hipGetLastError() == hipSuccess ? 0 : MDLS_EHIP;
 }
 
@@ -2093,18 +2183,24 @@ int batch_solve_t(int count, double *A, double *b, double *x, int variant, void 
 
 // ---------------------------------------------------------------- refined solve (host)
 // Least squares to PX limbs from a double-double factorisation: F := A, QR of F in dd (with
-// the tile T factors), the inverses of R's diagonal tiles (once), x := 0, r := b; then at most
-// `iters` steps: d := R^-1 (Q^T r)(0:n) in dd (r rounded to dd), x += d, r := b - A x in PX limbs,
+// the tile T factors), the inverses of R's diagonal tiles (once), then at most `iters` steps,
 // stopping on the device once the correction norms show convergence (k_refine_check; the
-// remaining steps' kernels return at once, so the call stays asynchronous).  Converges when
-// kappa(A) 2^-105 << 1; norms[2 it], norms[2 it + 1] receive max |d| and max |x| of step it, -1
-// for steps not taken.
+// remaining steps' kernels return at once, so the call stays asynchronous).
+//  * m == n (a square system is consistent): x := 0, r := b; each step d := R^-1 (Q^T r) in dd
+//    (r rounded to dd), x += d, r := b - A x in PX limbs.
+//  * m > n: refinement of the augmented system [I A; A^T 0][r; x] = [b; 0] (Bjorck 1967), which
+//    refines the residual with x, so that a nonzero residual does not limit the accuracy:
+//    x := 0, r := 0; each step f := b - r - A x and g := -A^T r in PX limbs, rounded to dd;
+//    h := R^-T g (forward substitution with the transposed tile inverses), d := Q^T f,
+//    dx := R^-1 (d(0:n) - h), dr := Q [h; d(n:m)], x += dx, r += dr.
+// Converges when kappa(A) 2^-105 << 1; norms[2 it], norms[2 it + 1] receive max |dx| and max |x|
+// of step it, -1 for steps not taken.
 inline size_t refine_extra_bytes(int px, int m, int n, int tile)
 {
     const size_t nch = (size_t)(n + kResidCols - 1) / kResidCols;
-    return sizeof(double) * (2 * (size_t)n * tile + (size_t)px * m + 2 * (size_t)m + 2 * (size_t)n + nch * px * m +
-                             4 * (size_t)tile * 64) +
-           7 * 256;
+    return sizeof(double) * (2 * (size_t)n * tile + 2 * (size_t)px * m + 2 * (size_t)m + 6 * (size_t)n +
+                             nch * px * m + 4 * (size_t)tile * 64) +
+           10 * 256;
 }
 
 template <int PX>
@@ -2120,37 +2216,74 @@ int refine_t(int m, int n, int tile, const double *A, int lda, const double *b, 
         return p;
     };
     const int nch = (n + kResidCols - 1) / kResidCols;
+    const bool aug = m > n;
     double *T = (double *)take(sizeof(double) * 2 * (size_t)n * tile);
-    double *r = (double *)take(sizeof(double) * (size_t)PX * m);
+    double *r = (double *)take(sizeof(double) * (size_t)PX * m);    // residual b - A x, or f
+    double *rr = (double *)take(sizeof(double) * (size_t)PX * m);   // augmented form: the residual iterate
     double *rdd = (double *)take(sizeof(double) * 2 * (size_t)m);
     double *dd = (double *)take(sizeof(double) * 2 * (size_t)n);
+    double *gdd = (double *)take(sizeof(double) * 2 * (size_t)n);
+    double *hdd = (double *)take(sizeof(double) * 2 * (size_t)n);
     double *part = (double *)take(sizeof(double) * (size_t)nch * PX * m);
     double *S = (double *)take(sizeof(double) * 4 * (size_t)tile * 64);
     int *done = (int *)take(sizeof(int) * 4);
     double *U = S + 2 * (size_t)tile * 64;
     const long psa = (long)lda * n;
+    const int N = n / tile;
     MDLS_LAUNCH("k_copy", PX, 0, k_copy, dim3((unsigned)((psa + 255) / 256)), dim3(256), s, A, psa, F, psa, (int)psa, 2);
     MDLS_LAUNCH("k_copy", PX, 0, k_copy, dim3((m + 255) / 256), dim3(256), s, b, (long)m, r, (long)m, m, PX);
     MDLS_LAUNCH("k_zero", PX, 0, k_zero_f64, dim3((PX * n + 255) / 256), dim3(256), s, x, (long)PX * n);
+    if (aug) {
+        MDLS_LAUNCH("k_zero", PX, 0, k_zero_f64, dim3((PX * m + 255) / 256), dim3(256), s, rr, (long)PX * m);
+        MDLS_LAUNCH("k_zero", PX, 0, k_zero_f64, dim3((2 * n + 255) / 256), dim3(256), s, gdd, 2L * n);
+    }
     MDLS_LAUNCH("k_refine_init", PX, 0, k_refine_init, dim3((2 * iters + 255) / 256), dim3(256), s, norms, iters, done);
     int rc = qr_t<2>(m, n, tile, F, lda, nullptr, T, tile, ws, nullptr, s);
     if (rc != 0) return rc;
     double *Xinv = cx.big();
+    const long xips = (long)tile * n;
     backsub_prep<2>(cx, n, tile, F, lda, psa, Xinv, d_info);
     for (int it = 0; it < iters; ++it) {
         if (it > 0) {
+            // r := b - A x (square), f := b - r - A x and g := -A^T r (augmented), in PX limbs
             MDLS_LAUNCH("k_resid_part", PX, (double)m * n, (k_resid_part<2, PX>), dim3((m + kThreads - 1) / kThreads, nch),
                         dim3(kThreads), s, A, (long)lda, psa, m, n, x, (long)n, part, done);
             MDLS_LAUNCH("k_resid_fin", PX, 0, (k_resid_fin<PX>), dim3((m + kThreads - 1) / kThreads), dim3(kThreads), s, b,
-                        (long)m, part, m, nch, r, (long)m, done);
+                        (long)m, aug ? rr : nullptr, (long)m, part, m, nch, r, (long)m, done);
+            if (aug)
+                MDLS_LAUNCH("k_resid_t", PX, (double)m * n, (k_resid_t<2, PX, 2>), dim3((n + 3) / 4), dim3(kThreads), s, A,
+                            (long)lda, psa, m, n, rr, (long)m, gdd, (long)n, done);
         }
         MDLS_LAUNCH("k_copy", PX, 0, k_copy_if, dim3((m + 255) / 256), dim3(256), s, r, (long)m, rdd, (long)m, m, 2, done);
+        if (aug) {
+            // h := R^-T g: for each tile from the top, h_i = Xinv_i^T g_i, then g_j -= R_ij^T h_i
+            for (int i = 0; i < N; ++i) {
+                const long it0 = (long)i * tile;
+                MDLS_LAUNCH("k_bs_xi_t", PX, 0.5 * tile * tile, (k_bs_xi_t<2>), dim3((tile + 3) / 4), dim3(kThreads), s,
+                            Xinv + (long)i * tile * tile, (long)tile, xips, gdd + it0, (long)n, hdd + it0, (long)n, tile,
+                            done);
+                const int rest = n - (int)it0 - tile;
+                if (rest > 0)
+                    MDLS_LAUNCH("k_bs_upd_t", PX, (double)rest * tile, (k_bs_upd_t<2>), dim3((rest + 3) / 4),
+                                dim3(kThreads), s, F + (it0 + tile) * lda + it0, (long)lda, psa, hdd + it0, (long)n,
+                                gdd + it0 + tile, (long)n, rest, tile, done);
+            }
+        }
         apply_qt_blocks<2>(m, n, tile, F, lda, T, tile, rdd, m, 1, S, U, done, s);
-        MDLS_LAUNCH("k_copy", PX, 0, k_copy_if, dim3((n + 255) / 256), dim3(256), s, rdd, (long)m, cx.yw(), (long)n, n, 2,
-                    done);
+        if (aug)
+            MDLS_LAUNCH("k_aug_split", PX, 0, (k_aug_split<2>), dim3((n + kThreads - 1) / kThreads), dim3(kThreads), s,
+                        rdd, (long)m, hdd, (long)n, cx.yw(), (long)n, n, done);
+        else
+            MDLS_LAUNCH("k_copy", PX, 0, k_copy_if, dim3((n + 255) / 256), dim3(256), s, rdd, (long)m, cx.yw(), (long)n,
+                        n, 2, done);
         backsub_sweep<2>(cx, n, tile, F, lda, psa, Xinv, cx.yw(), dd, n, done);
         MDLS_LAUNCH("k_refine_add", PX, 0, (k_refine_add<PX, 2>), dim3((n + kThreads - 1) / kThreads), dim3(kThreads), s,
                     x, (long)n, dd, (long)n, n, (unsigned long long *)(norms + 2 * it), done);
+        if (aug) {
+            apply_q_blocks<2>(m, n, tile, F, lda, T, tile, rdd, m, 1, S, U, done, s);
+            MDLS_LAUNCH("k_md_add", PX, 0, (k_md_add<PX, 2>), dim3((m + kThreads - 1) / kThreads), dim3(kThreads), s, rr,
+                        (long)m, rdd, (long)m, m, done);
+        }
         MDLS_LAUNCH("k_refine_check", PX, 0, (k_refine_check<PX>), dim3(1), dim3(64), s, it, iters, norms, done);
     }
     MDLS_LAUNCH("k_fold_err", PX, 0, k_fold_err, dim3(1), dim3(64), s, cx.err(), d_info);
