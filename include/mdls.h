@@ -58,6 +58,7 @@ typedef enum { MDLS_F64 = 1, MDLS_DD = 2, MDLS_QD = 4, MDLS_OD = 8 } mdls_prec;
 
 #define MDLS_EHIP (-100)        /* a kernel launch failed */
 #define MDLS_EUNSUPPORTED (-101) /* valid arguments outside what the library handles */
+#define MDLS_ESCRATCH (-102)     /* mdls_solve_noalloc: the workspace would exceed its static scratch */
 
 /*
  * Set-up of the calling host thread on the current device: creates the look-ahead side stream
@@ -184,6 +185,26 @@ int mdls_backsub(int p, int n, int tile, const double *R, int ldr, double *x, vo
  */
 int mdls_solve(int p, int m, int n, int tile, double *A, int lda, double *b, double *x,
                void *ws, size_t ws_bytes, int *d_info, hipStream_t stream);
+
+/*
+ * mdls_solve without a workspace argument, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels, in the same order, with the same results bit for bit, but the workspace is a
+ * static device array of MDLS_NOALLOC_SCRATCH_BYTES bytes inside the library, which each GPU
+ * the library runs on holds until the process ends.  The call itself allocates nothing (no
+ * hipMalloc, no stream, no event; launch timing is not recorded for it).  Its device address
+ * is looked up once per device by mdls_init, or by the first call on a device if mdls_init was
+ * not called there (make that first call outside graph capture).
+ * Arguments as mdls_solve without ws and ws_bytes: -1..-9 for arguments 1..9 (d_info is
+ * argument 9).  Returns MDLS_ESCRATCH when mdls_workspace_bytes(p, m, n, tile) exceeds
+ * MDLS_NOALLOC_SCRATCH_BYTES (every square or tall n = 1024 solve fits, as does m = n = 2048
+ * up to octo double).  Every call on one GPU shares that GPU's scratch and leaves its contents
+ * behind (the solve clears what must start at zero itself): calls that overlap on one GPU, on
+ * any streams or threads, race and give undefined results.
+ */
+#define MDLS_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int mdls_solve_noalloc(int p, int m, int n, int tile, double *A, int lda, double *b, double *x, int *d_info,
+                       hipStream_t stream);
 
 /* Static text for a status code. */
 const char *mdls_status_string(int status);

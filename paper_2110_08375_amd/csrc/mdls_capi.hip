@@ -54,7 +54,10 @@ hipEvent_t pool_get()
 }  // namespace
 
 namespace mdls_impl {
-bool timing_on() { return g_on; }
+namespace {
+thread_local int t_timing_off = 0;  // set inside calls that must not create timing events
+}
+bool timing_on() { return g_on && !t_timing_off; }
 
 // Side streams: one per (host thread, device), created by mdls_init and destroyed by
 // mdls_finalize; a solve never creates one.
@@ -236,6 +239,34 @@ struct BacksubF {
     static int run(A... a) { return backsub_t<P>(a...); }
 };
 
+}  // namespace
+
+// ============================================================================ static scratch
+// Device memory of the allocation-free solve: a file-scope array of every device's code object,
+// held until the process ends.  Host code never passes the array's name to a kernel (on the
+// host it is only a stand-in); it passes the device address hipGetSymbolAddress returns, looked
+// up once per device with that device current.
+static __device__ __align__(256) char scratch[MDLS_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+std::atomic<char *> g_scratch_ptr[kMaxDev];
+
+// the device address of this device's scratch array; null if the lookup fails
+char *scratch_ptr()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDev) return nullptr;
+    char *p = g_scratch_ptr[dev].load(std::memory_order_acquire);
+    if (p) return p;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    p = g_scratch_ptr[dev].load(std::memory_order_relaxed);
+    if (p) return p;
+    void *q = nullptr;
+    if (hipGetSymbolAddress(&q, HIP_SYMBOL(scratch)) != hipSuccess || !q) return nullptr;
+    g_scratch_ptr[dev].store((char *)q, std::memory_order_release);
+    return (char *)q;
+}
 }  // namespace
 
 // ============================================================================ C ABI
@@ -514,6 +545,31 @@ int mdls_solve(int p, int m, int n, int tile, double *A, int lda, double *b, dou
     return dispatch<SolveF>(p, m, n, tile, A, lda, b, x, ws, d_info, stream);
 }
 
+int mdls_solve_noalloc(int p, int m, int n, int tile, double *A, int lda, double *b, double *x, int *d_info,
+                       hipStream_t stream)
+{
+    if (!valid_p(p)) return -1;
+    if (m < 1) return -2;
+    if (n < 1 || n > m) return -3;
+    if (!valid_tile(tile) || n % tile != 0) return -4;
+    if (!A) return -5;
+    if (lda < m) return -6;
+    if (!b) return -7;
+    if (!x) return -8;
+    if (!d_info) return -9;
+    if (mdls_workspace_bytes(p, m, n, tile) > (size_t)MDLS_NOALLOC_SCRATCH_BYTES) return MDLS_ESCRATCH;
+    if (m > mdls_max_rows(p) || panel_groups(p, m) > panel_capacity(p)) return MDLS_EUNSUPPORTED;
+    char *ws = scratch_ptr();
+    if (!ws) return MDLS_EHIP;
+    // the solve clears its barrier counters and error flags with kernels before using them, so
+    // what an earlier call left in the scratch does not matter; launch timing would create
+    // events, so it is not recorded for this call
+    t_timing_off = 1;
+    const int rc = dispatch<SolveF>(p, m, n, tile, A, lda, b, x, (void *)ws, d_info, stream);
+    t_timing_off = 0;
+    return rc;
+}
+
 size_t mdls_batch_workspace_bytes(int p, int count)
 {
     if (batch_variants(p) == 0 || count < 1) return 0;
@@ -663,6 +719,7 @@ int mdls_init(void)
         return MDLS_EHIP;
     for (int P : {1, 2, 4, 8})
         if (panel_capacity(P) < 1) return MDLS_EHIP;
+    if (!scratch_ptr()) return MDLS_EHIP;
     p.ok = true;
     return 0;
 }
@@ -790,6 +847,8 @@ const char *mdls_status_string(int status)
     if (status == 0) return "success";
     if (status == MDLS_EHIP) return "a HIP kernel launch failed";
     if (status == MDLS_EUNSUPPORTED) return "arguments valid but outside what the library supports";
+    if (status == MDLS_ESCRATCH)
+        return "the problem's workspace exceeds the static scratch of mdls_solve_noalloc (MDLS_NOALLOC_SCRATCH_BYTES)";
     if (status < 0 && status > -20) return "invalid argument (the negated status is its 1-based position)";
     return "unknown status";
 }

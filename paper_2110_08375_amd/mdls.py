@@ -15,7 +15,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libmdls.so")
 
 MDLS_F64, MDLS_DD, MDLS_QD, MDLS_OD = 1, 2, 4, 8
-MDLS_EHIP, MDLS_EUNSUPPORTED = -100, -101
+MDLS_EHIP, MDLS_EUNSUPPORTED, MDLS_ESCRATCH = -100, -101, -102
+MDLS_NOALLOC_SCRATCH_BYTES = 64 << 20
 MDLS_TUNE_LOOKAHEAD, MDLS_TUNE_PANEL_VARIANT, MDLS_TUNE_APPLY_GRID_CAP = 1, 2, 3
 MDLS_TUNE_APPLY_WIDE_ROWS, MDLS_TUNE_SPIN_LIMIT = 4, 5
 
@@ -26,7 +27,8 @@ EXPORTS = ("mdls_init", "mdls_finalize", "mdls_set_tuning", "mdls_get_tuning", "
            "mdls_solve_batched", "mdls_batch_variants", "mdls_batch_autotune", "mdls_wall_clock_khz",
            "mdls_refined_workspace_bytes", "mdls_solve_refined", "mdls_apply_q", "mdls_form_q",
            "mdls_cworkspace_bytes", "mdls_cqr", "mdls_capply_qh", "mdls_cbacksub", "mdls_csolve",
-           "mdls_dd_gemm_tn_workspace_bytes", "mdls_dd_gemm_tn", "mdls_capply_q", "mdls_cform_q")
+           "mdls_dd_gemm_tn_workspace_bytes", "mdls_dd_gemm_tn", "mdls_capply_q", "mdls_cform_q",
+           "mdls_solve_noalloc")
 
 
 class BatchDesc(ctypes.Structure):
@@ -66,6 +68,7 @@ def lib():
         L.mdls_form_q.argtypes = [i, i, i, i, vp, i, vp, i, vp, i, i, vp, sz, vp]
         L.mdls_backsub.argtypes = [i, i, i, vp, i, vp, vp, sz, vp, vp]
         L.mdls_solve.argtypes = [i, i, i, i, vp, i, vp, vp, vp, sz, vp, vp]
+        L.mdls_solve_noalloc.argtypes = [i, i, i, i, vp, i, vp, vp, vp, vp]
         L.mdls_status_string.argtypes = [i]
         L.mdls_status_string.restype = ctypes.c_char_p
         L.mdls_timing_enable.argtypes = [i]
@@ -276,6 +279,21 @@ def solve(p: int, A, b, tile: int, x=None, ws=None, info=None):
     rc = lib().mdls_solve(p, m, n, tile, _ptr(A), m, _ptr(b), _ptr(x), _ptr(ws), ws.numel(), _ptr(info),
                           _stream())
     _check(rc, "mdls_solve")
+    return x, info
+
+
+def solve_noalloc(p: int, A, b, tile: int, x, info):
+    """mdls_solve on the library's static scratch: A (P, n, m) and b (P, m) are overwritten,
+    x (P, n) and info (one int32) are caller-allocated; nothing is allocated here."""
+    import torch
+
+    m, n = _mat(A, p, "A")
+    _vec(b, p, "b", m)
+    _vec(x, p, "x", n)
+    if info is None or info.dtype != torch.int32 or info.numel() < 1 or info.device != A.device:
+        raise MdlsError("info must be an int32 tensor on the device of A")
+    rc = lib().mdls_solve_noalloc(p, m, n, tile, _ptr(A), m, _ptr(b), _ptr(x), _ptr(info), _stream())
+    _check(rc, "mdls_solve_noalloc")
     return x, info
 
 

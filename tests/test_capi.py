@@ -65,6 +65,24 @@ def test_solve_argument_errors(L):
     assert s(2, big, 32, 16, dummy, big, dummy, dummy, dummy, wsb, dummy, None) == -101
 
 
+def test_noalloc_argument_errors(L):
+    """mdls_solve_noalloc checks its arguments and its scratch limit on the host, before it looks
+    up its static scratch or enqueues anything."""
+    from paper_2110_08375_amd import mdls
+
+    d = ctypes.c_void_p(16)  # never dereferenced: validation fails first
+    s = L.mdls_solve_noalloc
+    assert s(3, 64, 32, 16, d, 64, d, d, d, None) == -1
+    assert s(2, 64, 32, 12, d, 64, d, d, d, None) == -4
+    assert s(2, 64, 32, 16, d, 63, d, d, d, None) == -6
+    assert s(2, 64, 32, 16, d, 64, d, d, None, None) == -9
+    # the largest workload that fits, and one that does not
+    assert L.mdls_workspace_bytes(8, 2048, 2048, 128) <= mdls.MDLS_NOALLOC_SCRATCH_BYTES
+    assert L.mdls_workspace_bytes(8, 4096, 2048, 256) > mdls.MDLS_NOALLOC_SCRATCH_BYTES
+    assert s(8, 4096, 2048, 256, d, 4096, d, d, d, None) == mdls.MDLS_ESCRATCH
+    assert "static scratch" in mdls.status_string(mdls.MDLS_ESCRATCH)
+
+
 def test_other_entry_point_errors(L):
     vp = ctypes.c_void_p
     d = vp(16)
