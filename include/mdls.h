@@ -78,7 +78,9 @@ int mdls_finalize(void);
  * the spin limit, how long a grid barrier waits before it reports -1 through *d_info.
  *   MDLS_TUNE_LOOKAHEAD        1 (default): concurrent trailing update after mdls_init; 0: off
  *   MDLS_TUNE_PANEL_VARIANT    0 (default) or 1: the panel kernel's alternative shape (more rows
- *                              per thread: dd 512 x 8, qd 256 x 4, od 256 x 2 threads x rows)
+ *                              per thread: dd 512 x 8, qd 256 x 4, od 256 x 2 threads x rows);
+ *                              octo-double factorisations of more than 1024 rows use the
+ *                              alternative shape under either value
  *   MDLS_TUNE_APPLY_GRID_CAP   workgroups of the concurrent trailing update; 0 (default): 448
  *                              (two per CU on 224 CUs), for od 224 once fewer than
  *                              MDLS_TUNE_APPLY_WIDE_ROWS (default 768) rows remain

@@ -112,11 +112,11 @@ int apply_grid_cap(int P, int h)
     return h >= t.apply_wide_rows ? 448 : 224;
 }
 
-int panel_capacity(int P)
+int panel_capacity(int P, int m)
 {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDev) return 0;
-    const int v = tuning().panel_variant ? 1 : 0;
+    const int v = panel_variant_for(P, m);
     std::atomic<int> &slot = g_capacity[dev][pidx(P)][v];
     int c = slot.load(std::memory_order_relaxed);
     if (c > 0) return c;
@@ -275,7 +275,8 @@ extern "C" {
 int mdls_max_rows(int p)
 {
     if (!valid_p(p)) return 0;
-    const PanelCfg cf = panel_cfg(p);
+    // the shape of the largest factorisations
+    const PanelCfg cf = panel_cfg_for(p, 1 << 30);
     return kGMax * (cf.nt / leaf_width(p)) * cf.r;
 }
 
@@ -297,7 +298,7 @@ int mdls_qr(int p, int m, int n, int tile, double *A, int lda, double *beta, dou
     if (T && ldt < tile) return -9;
     if (!ws) return -10;
     if (ws_bytes < mdls_workspace_bytes(p, m, n, tile)) return -11;
-    if (m > mdls_max_rows(p) || panel_groups(p, m) > panel_capacity(p)) return MDLS_EUNSUPPORTED;
+    if (m > mdls_max_rows(p) || panel_groups(p, m) > panel_capacity(p, m)) return MDLS_EUNSUPPORTED;
     return dispatch<QrF>(p, m, n, tile, A, lda, beta, T, ldt, ws, d_info, stream);
 }
 
@@ -541,7 +542,7 @@ int mdls_solve(int p, int m, int n, int tile, double *A, int lda, double *b, dou
     if (!ws) return -9;
     if (ws_bytes < mdls_workspace_bytes(p, m, n, tile)) return -10;
     if (!d_info) return -11;
-    if (m > mdls_max_rows(p) || panel_groups(p, m) > panel_capacity(p)) return MDLS_EUNSUPPORTED;
+    if (m > mdls_max_rows(p) || panel_groups(p, m) > panel_capacity(p, m)) return MDLS_EUNSUPPORTED;
     return dispatch<SolveF>(p, m, n, tile, A, lda, b, x, ws, d_info, stream);
 }
 
@@ -558,7 +559,7 @@ int mdls_solve_noalloc(int p, int m, int n, int tile, double *A, int lda, double
     if (!x) return -8;
     if (!d_info) return -9;
     if (mdls_workspace_bytes(p, m, n, tile) > (size_t)MDLS_NOALLOC_SCRATCH_BYTES) return MDLS_ESCRATCH;
-    if (m > mdls_max_rows(p) || panel_groups(p, m) > panel_capacity(p)) return MDLS_EUNSUPPORTED;
+    if (m > mdls_max_rows(p) || panel_groups(p, m) > panel_capacity(p, m)) return MDLS_EUNSUPPORTED;
     char *ws = scratch_ptr();
     if (!ws) return MDLS_EHIP;
     // the solve clears its barrier counters and error flags with kernels before using them, so
@@ -700,7 +701,7 @@ int mdls_solve_refined(int p_out, int m, int n, int tile, const double *A, int l
     if (ws_bytes < mdls_refined_workspace_bytes(p_out, m, n, tile)) return -12;
     if (!d_info) return -13;
     if (!d_norms) return -14;
-    if (m > mdls_max_rows(2) || panel_groups(2, m) > panel_capacity(2)) return MDLS_EUNSUPPORTED;
+    if (m > mdls_max_rows(2) || panel_groups(2, m) > panel_capacity(2, m)) return MDLS_EUNSUPPORTED;
     if (p_out == 4) return refine_t<4>(m, n, tile, A, lda, b, x, iters, F, ws, d_info, d_norms, stream);
     return refine_t<8>(m, n, tile, A, lda, b, x, iters, F, ws, d_info, d_norms, stream);
 }
@@ -718,7 +719,7 @@ int mdls_init(void)
         hipEventCreateWithFlags(&p.ss.ev_wide[1], hipEventDisableTiming) != hipSuccess)
         return MDLS_EHIP;
     for (int P : {1, 2, 4, 8})
-        if (panel_capacity(P) < 1) return MDLS_EHIP;
+        if (panel_capacity(P, 1) < 1 || panel_capacity(P, 1 << 30) < 1) return MDLS_EHIP;
     if (!scratch_ptr()) return MDLS_EHIP;
     p.ok = true;
     return 0;

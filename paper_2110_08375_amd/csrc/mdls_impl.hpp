@@ -611,7 +611,12 @@ __global__ __launch_bounds__(NT) void k_panel(PanelArgs g)
 //   k_apply_u -- each unit's rows: c -= Y U.
 // All three walk their units grid-stride, so a capped grid leaves CUs free for a concurrent
 // panel.  Y is staged through LDS per unit; lanes walk rows (unit-stride limb planes).
-constexpr int kRB = 256;  // most rows per unit
+// most rows per unit: 256, or 128 where W P 256 doubles of staged Y would exceed 64 KiB of LDS
+template <int P, int W>
+constexpr int rb_max()
+{
+    return W * P * 256 * 8 <= 65536 ? 256 : 128;
+}
 
 struct ApplyArgs {
     const double *Y;  // panel top-left (diagonal) element; Y is unit lower trapezoidal
@@ -626,7 +631,7 @@ struct ApplyArgs {
     long ldb, psb;
     int nb;
     int c0, ncol;  // this launch covers columns c0 .. c0 + ncol - 1 of the (C, B) index space
-    int rb, nrb;   // rows per unit (a multiple of 64, at most kRB) and row blocks
+    int rb, nrb;   // rows per unit (a multiple of 64, at most rb_max) and row blocks
     double *part;  // [ncol][nrb][W][P] partial sums
     double *nu;    // [ncol][W][P] -U
 };
@@ -651,7 +656,7 @@ __device__ __forceinline__ void stage_y(const ApplyArgs &g, double *sY, long r0,
         const int r = e % g.rb, i = e / g.rb;
         const V<P> y = y_entry<P>(g.Y, g.ldy, g.psy, r0 + r, i, g.h, g.wact);
 #pragma unroll
-        for (int k = 0; k < P; ++k) sY[(i * P + k) * kRB + r] = y.x[k];
+        for (int k = 0; k < P; ++k) sY[(i * P + k) * rb_max<P, W>() + r] = y.x[k];
     }
 }
 
@@ -689,10 +694,20 @@ __device__ __forceinline__ void reduce_scatter(Acc<P> (&s)[W], int lane)
     reduce_scatter_level<P, W, W / 2, 32>(s, lane);
 }
 
+// Accumulators a lane keeps at once in k_apply_s: all W, or for octo double at most 4 (the
+// partial sums of the other columns of Y take further passes over the unit's rows), so that
+// the kernel keeps two waves per SIMD.
 template <int P, int W>
-__global__ __launch_bounds__(kThreads) void k_apply_s(ApplyArgs g)
+constexpr int apply_pass_width()
 {
-    __shared__ double sY[W * P * kRB];
+    return (P >= 8 && W > 4) ? 4 : W;
+}
+
+template <int P, int W>
+__global__ __launch_bounds__(kThreads, 2) void k_apply_s(ApplyArgs g)
+{
+    constexpr int WH = apply_pass_width<P, W>();
+    __shared__ double sY[W * P * rb_max<P, W>()];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int ncg = (g.ncol + 3) / 4;
     const int units = ncg * g.nrb;
@@ -706,30 +721,33 @@ __global__ __launch_bounds__(kThreads) void k_apply_s(ApplyArgs g)
         long cps = 0;
         const double *col = apply_col(g, gc, &cps);
         if (!col) continue;  // whole wave
-        Acc<P> s[W];
+#pragma unroll 1
+        for (int i0 = 0; i0 < W; i0 += WH) {
+            Acc<P> s[WH];
 #pragma unroll
-        for (int i = 0; i < W; ++i) s[i] = acc_zero<P>();
-        int nterm = 0;
-        for (int r = lane; r < g.rb; r += 64) {
-            const long gr = r0 + r;
-            if (gr < g.h) {
-                const V<P> cv = ldm<P>(col, cps, gr);
+            for (int i = 0; i < WH; ++i) s[i] = acc_zero<P>();
+            int nterm = 0;
+            for (int r = lane; r < g.rb; r += 64) {
+                const long gr = r0 + r;
+                if (gr < g.h) {
+                    const V<P> cv = ldm<P>(col, cps, gr);
 #pragma unroll
-                for (int i = 0; i < W; ++i) {
-                    V<P> y;
+                    for (int i = 0; i < WH; ++i) {
+                        V<P> y;
 #pragma unroll
-                    for (int k = 0; k < P; ++k) y.x[k] = sY[(i * P + k) * kRB + r];
-                    acc_fma_step(s[i], y, cv, nterm);
+                        for (int k = 0; k < P; ++k) y.x[k] = sY[((i0 + i) * P + k) * rb_max<P, W>() + r];
+                        acc_fma_step(s[i], y, cv, nterm);
+                    }
+                    ++nterm;
                 }
-                ++nterm;
             }
-        }
-        reduce_scatter<P, W>(s, lane);
-        constexpr int LPI = 64 / W;
-        if (lane % LPI == 0) {
-            double *dst = g.part + (((long)gc * g.nrb + rbk) * W + lane / LPI) * P;
+            reduce_scatter<P, WH>(s, lane);
+            constexpr int LPI = 64 / WH;
+            if (lane % LPI == 0) {
+                double *dst = g.part + (((long)gc * g.nrb + rbk) * W + i0 + lane / LPI) * P;
 #pragma unroll
-            for (int k = 0; k < P; ++k) dst[k] = s[0].s[k];
+                for (int k = 0; k < P; ++k) dst[k] = s[0].s[k];
+            }
         }
     }
 }
@@ -778,7 +796,8 @@ __global__ __launch_bounds__(kThreads) void k_apply_t(ApplyArgs g)
 template <int P, int W>
 __global__ __launch_bounds__(kThreads) void k_apply_u(ApplyArgs g)
 {
-    __shared__ double sY[W * P * kRB];
+    __shared__ double sY[W * P * rb_max<P, W>()];
+    __shared__ double sU[4][W * P];  // -U of each wave's column
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int ncg = (g.ncol + 3) / 4;
     const int units = ncg * g.nrb;
@@ -787,16 +806,12 @@ __global__ __launch_bounds__(kThreads) void k_apply_u(ApplyArgs g)
         const long r0 = (long)rbk * g.rb;
         __syncthreads();
         stage_y<P, W>(g, sY, r0, tid);
-        __syncthreads();
         const int gc = cg * 4 + wid;
+        if (gc < g.ncol && lane < W * P) sU[wid][lane] = g.nu[(long)gc * W * P + lane];
+        __syncthreads();
         long cps = 0;
         double *col = apply_col(g, gc, &cps);
         if (!col) continue;  // whole wave
-        V<P> nU[W];
-#pragma unroll
-        for (int i = 0; i < W; ++i)
-#pragma unroll
-            for (int k = 0; k < P; ++k) nU[i].x[k] = g.nu[((long)gc * W + i) * P + k];
         for (int r = lane; r < g.rb; r += 64) {
             const long gr = r0 + r;
             if (gr < g.h) {
@@ -805,8 +820,8 @@ __global__ __launch_bounds__(kThreads) void k_apply_u(ApplyArgs g)
                 for (int i = 0; i < W; ++i) {
                     V<P> y;
 #pragma unroll
-                    for (int k = 0; k < P; ++k) y.x[k] = sY[(i * P + k) * kRB + r];
-                    acc_fma(t, y, nU[i]);
+                    for (int k = 0; k < P; ++k) y.x[k] = sY[(i * P + k) * rb_max<P, W>() + r];
+                    acc_fma(t, y, lds_ld<P>(&sU[wid][i * P]));
                 }
                 stm(col, cps, gr, acc_get(t));
             }
@@ -1277,11 +1292,13 @@ __global__ __launch_bounds__(kThreads) void k_invert(InvArgs g)
             d = recip(ldm<P>(U, g.psu, (long)i * g.ldu + i));
         lds_st(&sD[i * P], d);
     }
-    V<P> r[RPT];
+    // the rows' right-hand sides stay lazy accumulators (level sums), renormalised every
+    // kLazy<P> steps and when their row is published
+    Acc<P> r[RPT];
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
         const int k = rg + q * RG;
-        r[q] = (k == j) ? from_double<P>(1.0) : zero<P>();
+        r[q] = acc_from((k == j) ? from_double<P>(1.0) : zero<P>());
         if (j < g.tile && k < g.tile && k > j) stm(X, g.psx, (long)j * g.ldx + k, zero<P>());
     }
     if (c1 > 0 && tid < c1 - 1) lds_st(&sU[(c1 - 1) & 1][tid * P], ldm<P>(U, g.psu, (long)(c1 - 1) * g.ldu + tid));
@@ -1298,17 +1315,21 @@ __global__ __launch_bounds__(kThreads) void k_invert(InvArgs g)
             V<P> xv = zero<P>();
 #pragma unroll
             for (int q = 0; q < RPT; ++q)
-                if (q == qi) xv = mul(r[q], lds_ld<P>(&sD[i * P]));
+                if (q == qi) xv = mul(acc_get(r[q]), lds_ld<P>(&sD[i * P]));
             lds_st(&sX[buf][jl * P], xv);
             stm(X, g.psx, (long)j * g.ldx + i, xv);
         }
         __syncthreads();
         if (j < c1 && j >= i) {
-            const V<P> xv = lds_ld<P>(&sX[buf][jl * P]);
+            const V<P> xv = neg(lds_ld<P>(&sX[buf][jl * P]));
+            const bool renorm = ((c1 - i) % kLazy<P>) == 0;
 #pragma unroll
             for (int q = 0; q < RPT; ++q) {
                 const int k = rg + q * RG;
-                if (k < i) r[q] = fma(r[q], neg(lds_ld<P>(&sU[buf][k * P])), xv);
+                if (k < i) {
+                    acc_fma(r[q], lds_ld<P>(&sU[buf][k * P]), xv);
+                    if (renorm) r[q] = acc_from(acc_get(r[q]));
+                }
             }
         }
         // sU[buf ^ 1] was last read in step i + 1, before this step's barrier
@@ -1381,27 +1402,41 @@ __global__ __launch_bounds__(kThreads) void k_bs_upd(const double *Rc, long ldr,
     const long row = (long)blockIdx.x * 64 + lane;
     const int q = (tile + 3) / 4;
     const int cb = wid * q, ce = min(tile, cb + q);
-    Acc<P> acc = acc_zero<P>();
+    // NA independent accumulators (column k goes to k mod NA), so that NA multiply-adds are
+    // in flight at once, added in a fixed order at the end
+    constexpr int NA = 4;
+    Acc<P> acc[NA];
+#pragma unroll
+    for (int a = 0; a < NA; ++a) acc[a] = acc_zero<P>();
     if (row < rows) {
         // B columns of R per batch; the next batch's loads are issued before the current
-        // batch's multiply-adds, so the HBM latency overlaps the dependent accumulation
-        constexpr int B = 32 / P;
+        // batch's multiply-adds, so the HBM latency overlaps the accumulation
+        constexpr int B = 32 / P < NA ? NA : 32 / P;
+        static_assert(B % NA == 0, "k_bs_upd batch");
         V<P> cur[B], nxt[B];
         auto load = [&](V<P> (&u)[B], int c) __attribute__((always_inline)) {
 #pragma unroll
             for (int k = 0; k < B; ++k) u[k] = (c + k < ce) ? ldm<P>(Rc, psr, (long)(c + k) * ldr + row) : zero<P>();
         };
         load(cur, cb);
+        int nt = 0;
         for (int c = cb; c < ce; c += B) {
             if (c + B < ce) load(nxt, c + B);
 #pragma unroll
             for (int k = 0; k < B; ++k)
-                if (c + k < ce) acc_fma_step(acc, cur[k], lds_ld<P>(&sx[(c + k) * P]), c + k - cb);
+                if (c + k < ce) acc_fma(acc[k % NA], cur[k], lds_ld<P>(&sx[(c + k) * P]));
+            nt += B / NA;
+            if (nt % kLazy<P> == 0) {
+#pragma unroll
+                for (int a = 0; a < NA; ++a) acc[a] = acc_from(acc_get(acc[a]));
+            }
 #pragma unroll
             for (int k = 0; k < B; ++k) cur[k] = nxt[k];
         }
+#pragma unroll
+        for (int a = 1; a < NA; ++a) acc_add_acc(acc[0], acc[a]);
     }
-    lds_st(&sp[wid][lane * P], acc_get(acc));
+    lds_st(&sp[wid][lane * P], acc_get(acc[0]));
     __syncthreads();
     if (wid == 0 && row < rows) {
         V<P> s = lds_ld<P>(&sp[0][lane * P]);
@@ -1559,7 +1594,7 @@ Tuning tuning();
 int apply_grid_cap(int P, int h);
 // Workgroups of the panel kernel of precision P (current variant) that can be resident at once on
 // the current device (occupancy x compute units); 0 if the device cannot be queried.
-int panel_capacity(int P);
+int panel_capacity(int P, int m);
 
 #define MDLS_LAUNCH(NAME, PREC, WORK, KERNEL, GRID, BLOCK, STREAM, ...)                       \
     do {                                                                                     \
@@ -1590,7 +1625,7 @@ struct Cfg<4> {
 };
 template <>
 struct Cfg<8> {
-    static constexpr int W = 4, NCI = 4;
+    static constexpr int W = 8, NCI = 4;
 };
 
 inline int leaf_width(int P)
@@ -1676,12 +1711,15 @@ inline PanelCfg panel_cfg(int P, int variant)
     }
 }
 
-inline PanelCfg panel_cfg(int P) { return panel_cfg(P, tuning().panel_variant); }
+// The shape an m-row factorisation uses: the tuning variant, except that octo-double panels of
+// more than 1024 rows always hold two rows per thread (half the workgroups, which leaves more
+// compute units to the concurrent trailing update; measured on the 2048 x 1024 solve).
+inline int panel_variant_for(int P, int m) { return (tuning().panel_variant || (P >= 8 && m > 1024)) ? 1 : 0; }
+inline PanelCfg panel_cfg_for(int P, int m) { return panel_cfg(P, panel_variant_for(P, m)); }
 
-// Workgroups of the largest panel launch of an m-row factorisation.
 inline int panel_groups(int P, int m)
 {
-    const PanelCfg cf = panel_cfg(P);
+    const PanelCfg cf = panel_cfg_for(P, m);
     const int rows_per_wg = cf.nt / leaf_width(P) * cf.r;
     const int g = (m + rows_per_wg - 1) / rows_per_wg;
     return g < 1 ? 1 : g;
@@ -1747,7 +1785,7 @@ void launch_apply(const Ctx<P> &cx, ApplyArgs aa, int grid_cap, hipStream_t st)
         aa.c0 = c0;
         aa.ncol = (ntot - c0 < cx.L.acols) ? (ntot - c0) : cx.L.acols;
         const int ncg = (aa.ncol + 3) / 4;
-        int rb = kRB;
+        int rb = rb_max<P, W>();
         while (rb > 64 && (long)ncg * ((aa.h + rb - 1) / rb) < 2L * kCUs) rb >>= 1;
         aa.rb = rb;
         aa.nrb = (aa.h + rb - 1) / rb;
@@ -1774,7 +1812,7 @@ template <int P>
 int qr_panels(const Ctx<P> &cx, int m, int n, double *A, long lda, long psa, double *B, long ldb, long psb, int nb)
 {
     constexpr int W = Cfg<P>::W;
-    const PanelCfg cf = panel_cfg(P);
+    const PanelCfg cf = panel_cfg_for(P, m);
     const int rows_per_wg = cf.nt / W * cf.r;
     const int nleaves = cx.L.nleaves;
     const Tuning tu = tuning();
