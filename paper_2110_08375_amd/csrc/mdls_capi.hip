@@ -714,13 +714,25 @@ int mdls_init(void)
     PerThread &p = t_side[dev];
     if (p.ok) return 0;
     if (hipStreamCreateWithFlags(&p.ss.q, hipStreamNonBlocking) != hipSuccess) return MDLS_EHIP;
-    if (hipEventCreateWithFlags(&p.ss.ev_panel, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&p.ss.ev_wide[0], hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&p.ss.ev_wide[1], hipEventDisableTiming) != hipSuccess)
-        return MDLS_EHIP;
+    // the events only order the two streams' kernels on this device: a device-scope release is
+    // enough, as neither the host nor another device waits on them
+    const unsigned evf = hipEventDisableTiming | hipEventReleaseToDevice;
+    hipEvent_t *evs[3] = {&p.ss.ev_panel, &p.ss.ev_wide[0], &p.ss.ev_wide[1]};
+    for (int e = 0; e < 3; ++e) {
+        if (hipEventCreateWithFlags(evs[e], evf) != hipSuccess) {
+            for (int f = 0; f < e; ++f) (void)hipEventDestroy(*evs[f]);
+            (void)hipStreamDestroy(p.ss.q);
+            return MDLS_EHIP;
+        }
+    }
+    bool ok = scratch_ptr() != nullptr;
     for (int P : {1, 2, 4, 8})
-        if (panel_capacity(P, 1) < 1 || panel_capacity(P, 1 << 30) < 1) return MDLS_EHIP;
-    if (!scratch_ptr()) return MDLS_EHIP;
+        ok = ok && panel_capacity(P, 1) > 0 && panel_capacity(P, 1 << 30) > 0;
+    if (!ok) {
+        for (int f = 0; f < 3; ++f) (void)hipEventDestroy(*evs[f]);
+        (void)hipStreamDestroy(p.ss.q);
+        return MDLS_EHIP;
+    }
     p.ok = true;
     return 0;
 }
