@@ -1337,6 +1337,95 @@ __global__ __launch_bounds__(kThreads) void k_invert(InvArgs g)
     }
 }
 
+// Blocked tile inversion (Algorithm 1, stage 1, for tiles of 64 rows or more): with the
+// 32 x 32 diagonal blocks U_II of every tile inverted first (k_invert, 32 dependent row steps
+// instead of one per row of the tile), the blocks of X = U^-1 above the diagonal follow by
+// block rows from the bottom, X_IK = -X_II sum_{I < J <= K} U_IJ X_JK.  Workgroup (slice, K - 1,
+// tile) forms block column K for NCB of its columns: thread (r, c) holds row r of the block
+// row being formed, column c.  The block column is kept in LDS; the diagonal blocks' inverses
+// come from Xd (nb x nb each, ld nb, tile t's block I at Xd + (t NB + I) nb^2, plane stride
+// dps).
+constexpr int kInvNB = 32;  // rows of a diagonal block
+
+template <int P>
+constexpr int inv_blk_cols()
+{
+    return P >= 8 ? 4 : 8;  // columns per workgroup: (tile rows x NCB x P) doubles of LDS <= 64 KiB
+}
+
+struct InvBlkArgs {
+    const double *U;  // tile t at U + t (tile ldu + tile)
+    long ldu, psu;
+    const double *Xd;  // diagonal-block inverses
+    long dps;
+    double *X;  // tile t at X + t tile^2, ld tile, plane stride psx
+    long psx;
+    int tile;
+    const int *skip;
+};
+
+template <int P>
+__global__ __launch_bounds__(kThreads) void k_inv_blocks(InvBlkArgs g)
+{
+    constexpr int NB = kInvNB, NCB = inv_blk_cols<P>();
+    constexpr int NTH = NB * NCB;  // threads that hold an entry
+    __shared__ double sX[256 * NCB * P];  // rows 0 .. (K+1) NB - 1 of this workgroup's columns
+    __shared__ double sR[NB * NCB * P];
+    if (g.skip && *g.skip) return;
+    const int tid = threadIdx.x;
+    const int r = tid % NB, c = tid / NB;
+    const int K = blockIdx.y + 1, t = blockIdx.z;
+    const int col = K * NB + blockIdx.x * NCB + c;  // column of the tile
+    const bool act = tid < NTH;
+    const long tt = (long)t * g.tile;
+    const double *U = g.U + tt * g.ldu + tt;
+    double *X = g.X + tt * g.tile;
+    const int nbt = g.tile / NB;
+    auto xd = [&](int I, int row, int k) __attribute__((always_inline)) {
+        return ldm<P>(g.Xd, g.dps, ((long)t * nbt + I) * NB * NB + (long)k * NB + row);
+    };
+    // the diagonal block X_KK: copied into place and into LDS (block column 1 also places X_00)
+    if (act) {
+        const V<P> v = xd(K, r, blockIdx.x * NCB + c);
+        lds_st(&sX[((K * NB + r) * NCB + c) * P], v);
+        stm(X, g.psx, (long)col * g.tile + K * NB + r, v);
+        if (K == 1) {
+            const int c0 = blockIdx.x * NCB + c;
+            stm(X, g.psx, (long)c0 * g.tile + r, xd(0, r, c0));
+        }
+    }
+    __syncthreads();
+    for (int I = K - 1; I >= 0; --I) {
+        // R(r, c) = sum over the rows k of block rows I+1 .. K of U(I NB + r, k) X(k, c)
+        if (act) {
+            Acc<P> a0 = acc_zero<P>(), a1 = acc_zero<P>();
+            const int k0 = (I + 1) * NB, k1 = (K + 1) * NB;
+            int nt = 0;
+            for (int k = k0; k < k1; k += 2) {
+                acc_fma(a0, ldm<P>(U, g.psu, (long)k * g.ldu + I * NB + r), lds_ld<P>(&sX[(k * NCB + c) * P]));
+                acc_fma(a1, ldm<P>(U, g.psu, (long)(k + 1) * g.ldu + I * NB + r), lds_ld<P>(&sX[((k + 1) * NCB + c) * P]));
+                if ((++nt) % kLazy<P> == 0) {
+                    a0 = acc_from(acc_get(a0));
+                    a1 = acc_from(acc_get(a1));
+                }
+            }
+            acc_add_acc(a0, a1);
+            lds_st(&sR[(r * NCB + c) * P], acc_get(a0));
+        }
+        __syncthreads();
+        // X_IK(r, c) = -sum_{k >= r} X_II(r, k) R(k, c)
+        if (act) {
+            Acc<P> a = acc_zero<P>();
+            int nt = 0;
+            for (int k = r; k < NB; ++k) acc_fma_step(a, xd(I, r, k), lds_ld<P>(&sR[(k * NCB + c) * P]), nt++);
+            const V<P> v = neg(acc_get(a));
+            lds_st(&sX[((I * NB + r) * NCB + c) * P], v);
+            stm(X, g.psx, (long)col * g.tile + I * NB + r, v);
+        }
+        __syncthreads();
+    }
+}
+
 // x_i := Xinv_i y_i, one wave per output row
 template <int P>
 __global__ __launch_bounds__(kThreads) void k_bs_xi(const double *Xi, long ldx, long psx, const double *y, long yps,
@@ -1351,6 +1440,71 @@ __global__ __launch_bounds__(kThreads) void k_bs_xi(const double *Xi, long ldx, 
     for (int c = row + lane; c < tile; c += 64) acc_fma_step(acc, ldm<P>(Xi, psx, (long)c * ldx + row), ldm<P>(y, yps, c), nt++);
     const V<P> s = wave_sum(acc_get(acc));
     if (lane == 0) stm(x, xps, row, s);
+}
+
+// The update of the sweep split over column slices, for more workgroups in flight: workgroup
+// (row block, slice cs) forms part[cs][row] = R(row, cols of slice cs) x_i(slice) for 64 rows,
+// the slice's columns split over the four waves (four accumulators per lane each); k_bs_comb then
+// subtracts the slices' partial sums from y in a fixed order.
+constexpr int kBsSlices = 4;
+
+template <int P>
+__global__ __launch_bounds__(kThreads) void k_bs_upd_part(const double *Rc, long ldr, long psr, const double *xi,
+                                                         long xps, double *part, long pps, int rows, int tile,
+                                                         const int *skip)
+{
+    __shared__ double sx[256 * P];
+    __shared__ double sp[4][64 * P];
+    if (skip && *skip) return;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int per = tile / kBsSlices;
+    const int s0 = blockIdx.y * per;
+    for (int c = threadIdx.x; c < per; c += kThreads) lds_st(&sx[c * P], ldm<P>(xi, xps, s0 + c));
+    __syncthreads();
+    const long row = (long)blockIdx.x * 64 + lane;
+    const int q = (per + 3) / 4;
+    const int cb = wid * q, ce = min(per, cb + q);
+    constexpr int NA = 4;
+    Acc<P> acc[NA];
+#pragma unroll
+    for (int a = 0; a < NA; ++a) acc[a] = acc_zero<P>();
+    if (row < rows) {
+        int nt = 0;
+        for (int c = cb; c < ce; c += NA) {
+            V<P> u[NA];
+#pragma unroll
+            for (int k = 0; k < NA; ++k) u[k] = (c + k < ce) ? ldm<P>(Rc, psr, (long)(s0 + c + k) * ldr + row) : zero<P>();
+#pragma unroll
+            for (int k = 0; k < NA; ++k)
+                if (c + k < ce) acc_fma(acc[k], u[k], lds_ld<P>(&sx[(c + k) * P]));
+            if ((++nt) % kLazy<P> == 0) {
+#pragma unroll
+                for (int a = 0; a < NA; ++a) acc[a] = acc_from(acc_get(acc[a]));
+            }
+        }
+#pragma unroll
+        for (int a = 1; a < NA; ++a) acc_add_acc(acc[0], acc[a]);
+    }
+    lds_st(&sp[wid][lane * P], acc_get(acc[0]));
+    __syncthreads();
+    if (wid == 0 && row < rows) {
+        V<P> v = lds_ld<P>(&sp[0][lane * P]);
+        for (int w = 1; w < 4; ++w) v = add(v, lds_ld<P>(&sp[w][lane * P]));
+        stm(part + (long)blockIdx.y * rows, pps, row, v);
+    }
+}
+
+// y(row) -= sum over the slices cs of part[cs][row] (in slice order)
+template <int P>
+__global__ __launch_bounds__(kThreads) void k_bs_comb(const double *part, long pps, double *y, long yps, int rows,
+                                                     const int *skip)
+{
+    if (skip && *skip) return;
+    const long row = (long)blockIdx.x * kThreads + threadIdx.x;
+    if (row >= rows) return;
+    V<P> v = ldm<P>(part, pps, row);
+    for (int cs = 1; cs < kBsSlices; ++cs) v = add(v, ldm<P>(part + (long)cs * rows, pps, row));
+    stm(y, yps, row, sub(ldm<P>(y, yps, row), v));
 }
 
 // The transposed sweep (forward substitution with R^T, whose diagonal tiles have the inverses
@@ -1668,7 +1822,8 @@ inline Layout layout(int P, int m, int n, int tile)
     L.apart = take(sizeof(double) * (size_t)P * L.W * L.acols * ((m + 63) / 64));
     L.anu = take(sizeof(double) * (size_t)P * L.W * L.acols);
     // back substitution inverses / Gram blocks (P x tile x n) or Q^T B scratch (2 x P x tile x 64)
-    const size_t big1 = sizeof(double) * (size_t)P * tile * n;
+    // tile inverses (P x tile x n), and for blocked inversion the 32 x 32 diagonal blocks' (P x 32 x n)
+    const size_t big1 = sizeof(double) * (size_t)P * (tile + (tile >= 64 ? kInvNB : 0)) * n;
     const size_t big2 = sizeof(double) * 2 * (size_t)P * tile * 64;
     L.big = take(big1 > big2 ? big1 : big2);
     L.total = off;
@@ -1910,12 +2065,42 @@ void backsub_prep(const Ctx<P> &cx, int n, int tile, const double *R, long ldr, 
     ia.ustride = (long)tile * (ldr + 1);
     ia.dsup = nullptr;
     ia.dps = 0;
-    ia.X = Xinv;
-    ia.ldx = tile;
-    ia.psx = xips;
-    ia.xstride = (long)tile * tile;
-    ia.tile = tile;
-    invert_tiles<P>(cx, ia, N);
+    if (tile < 64 || tile % kInvNB != 0) {
+        ia.X = Xinv;
+        ia.ldx = tile;
+        ia.psx = xips;
+        ia.xstride = (long)tile * tile;
+        ia.tile = tile;
+        invert_tiles<P>(cx, ia, N);
+        return;
+    }
+    // blocked: the 32 x 32 diagonal blocks first (into Xd, after the P planes of Xinv), then the
+    // blocks above them by block rows
+    double *Xd = Xinv + (long)P * xips;
+    const long dps = (long)kInvNB * n;
+    ia.ustride = (long)kInvNB * (ldr + 1);
+    ia.X = Xd;
+    ia.ldx = kInvNB;
+    ia.psx = dps;
+    ia.xstride = (long)kInvNB * kInvNB;
+    ia.tile = kInvNB;
+    invert_tiles<P>(cx, ia, n / kInvNB);
+    InvBlkArgs ib;
+    ib.U = R;
+    ib.ldu = ldr;
+    ib.psu = psr;
+    ib.Xd = Xd;
+    ib.dps = dps;
+    ib.X = Xinv;
+    ib.psx = xips;
+    ib.tile = tile;
+    ib.skip = nullptr;
+    constexpr int NCB = inv_blk_cols<P>();
+    const int nbt = tile / kInvNB;
+    double work = 0.0;  // md multiply-adds: per block column K, sum over I < K of (K - I) + 1 blocks
+    for (int K = 1; K < nbt; ++K) work += (double)(K * (K + 1) / 2 + K) * kInvNB * kInvNB * kInvNB;
+    MDLS_LAUNCH("k_inv_blocks", P, work * N, (k_inv_blocks<P>), dim3(kInvNB / NCB, nbt - 1, N), dim3(kThreads), cx.s,
+                ib);
 }
 
 // Stage 2 (Algorithm 1): for i = N-1 .. 0, x_i := U_i^-1 y_i, then y_j -= R_{j,i} x_i for every
@@ -1933,8 +2118,18 @@ void backsub_sweep(const Ctx<P> &cx, int n, int tile, const double *R, long ldr,
                     Xinv + (long)i * tile * tile, (long)tile, xips, y + it, yps, x + it, xps, tile, skip);
         if (i > 0) {
             const int rows = i * tile;
-            MDLS_LAUNCH("k_bs_upd", P, (double)rows * tile, (k_bs_upd<P>), dim3((rows + 63) / 64), dim3(kThreads), cx.s,
-                        R + it * ldr, ldr, psr, x + it, xps, y, yps, rows, tile, skip);
+            if (tile % (4 * kBsSlices) == 0) {
+                // the update split over column slices; partial sums in the trailing-update scratch
+                double *part = cx.apart();
+                MDLS_LAUNCH("k_bs_upd", P, (double)rows * tile, (k_bs_upd_part<P>), dim3((rows + 63) / 64, kBsSlices),
+                            dim3(kThreads), cx.s, R + it * ldr, ldr, psr, x + it, xps, part, (long)kBsSlices * rows,
+                            rows, tile, skip);
+                MDLS_LAUNCH("k_bs_comb", P, 0, (k_bs_comb<P>), dim3((rows + kThreads - 1) / kThreads), dim3(kThreads), cx.s,
+                            part, (long)kBsSlices * rows, y, yps, rows, skip);
+            } else {
+                MDLS_LAUNCH("k_bs_upd", P, (double)rows * tile, (k_bs_upd<P>), dim3((rows + 63) / 64), dim3(kThreads),
+                            cx.s, R + it * ldr, ldr, psr, x + it, xps, y, yps, rows, tile, skip);
+            }
         }
     }
 }
