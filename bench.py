@@ -240,6 +240,41 @@ def precision_run(M, dev, n=2048, tile=128):
     return out
 
 
+def split_run(M, dev):
+    """The precision form's split-limb product on the FP64 matrix cores against the same
+    double-double product Y^T C on the vector units, at the trailing-update shapes of the first
+    panel of the n = 1024 and n = 2048 double-double factorisations (w = 16 Householder vectors);
+    kernel times from the in-library HIP-event timing."""
+    import torch
+
+    import mdgen
+
+    out = {"workload": "double-double S = Y^T C at trailing-update shapes (h rows, w = 16, c columns): "
+                       "k_split_tn (exact slicing, v_mfma_f64_16x16x4f64) vs k_dense_tn2 (vector units)"}
+    for (h, c) in ((1024, 1008), (2048, 2032)):
+        Y = torch.from_numpy(mdgen.md_uniform(2, h, 16, 5100 + h, mdgen.STREAM_A)).to(dev)
+        C = torch.from_numpy(mdgen.md_uniform(2, h, c, 5100 + h, mdgen.STREAM_B)).to(dev)
+        res = {}
+        for method, kname in ((0, "k_dense_tn2"), (1, "k_split_tn")):
+            S = M.dd_gemm_tn(method, Y, C)
+            torch.cuda.synchronize()
+            M.timing_reset()
+            M.timing_enable(True)
+            for _ in range(5):
+                M.dd_gemm_tn(method, Y, C, S=S)
+            torch.cuda.synchronize()
+            M.timing_enable(False)
+            ms, cnt, work = M.timing_query(kname, 2)
+            res[kname + "_us"] = round(1e3 * ms / max(cnt, 1), 2)
+            if method == 1:
+                # 28 slice products of 16 x 16 x 4 per 16 x 16 tile and 4-row step: FP64 matrix flops
+                mf = 2.0 * 28 * 16 * 16 * 4 * ((c + 15) // 16) * ((h + 3) // 4)
+                res["k_split_tn_mfma_tflops"] = round(mf / (1e-3 * ms / max(cnt, 1)) / 1e12, 3)
+        out["h%d_c%d" % (h, c)] = res
+        log("split product h=%d c=%d: %s" % (h, c, res))
+    return out
+
+
 def scale_run(M, dev, tile=128):
     """The other plain-method workloads: the tall 2048 x 1024 least squares in dd/qd/od, and the
     back substitution at scale (upper-triangular qd, n = 17 920, tile 256, off-diagonals uniform
@@ -603,6 +638,8 @@ def main():
             batched[PNAME[P]] = batched_run(M, P, args.batch, 4000 + P, dev, 3, True)
 
     precision = None if args.no_precision else precision_run(M, dev)
+    if precision is not None:
+        precision["split_product"] = split_run(M, dev)
     cplx = None if args.no_complex else complex_run(M, dev)
     scale = None if args.no_scale else scale_run(M, dev)
 

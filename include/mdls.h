@@ -73,9 +73,10 @@ int mdls_finalize(void);
 
 /*
  * Process-wide tuning, for benchmarks and tests; the defaults are built in and nothing is
- * read from the environment.  Only MDLS_TUNE_PANEL_VARIANT changes results (it changes the
- * panel's workgroup shape and so its reduction order); the others change only speed or, for
- * the spin limit, how long a grid barrier waits before it reports -1 through *d_info.
+ * read from the environment.  Only MDLS_TUNE_PANEL_VARIANT and MDLS_TUNE_SPLIT_UPDATE change
+ * results (the panel's workgroup shape and so its reduction order; the rounding of the update
+ * products); the others change only speed or, for the spin limit, how long a grid barrier waits
+ * before it reports -1 through *d_info.
  *   MDLS_TUNE_LOOKAHEAD        1 (default): concurrent trailing update after mdls_init; 0: off
  *   MDLS_TUNE_PANEL_VARIANT    0 (default) or 1: the panel kernel's alternative shape (more rows
  *                              per thread: dd 512 x 8, qd 256 x 4, od 256 x 2 threads x rows);
@@ -86,6 +87,12 @@ int mdls_finalize(void);
  *                              MDLS_TUNE_APPLY_WIDE_ROWS (default 768) rows remain
  *   MDLS_TUNE_SPIN_LIMIT       polls (each after a sleep of about 64 cycles) before a grid
  *                              barrier gives up; default 2^22
+ *   MDLS_TUNE_SPLIT_UPDATE     0 (default) or 1: mdls_solve_refined's double-double factorisation
+ *                              forms its trailing-update products Y^T C on the FP64 matrix cores
+ *                              by exact slicing (the product of mdls_dd_gemm_tn method 1) instead
+ *                              of on the vector units; the products are exactly rounded either
+ *                              way up to the vector units' lazy accumulation, so results differ
+ *                              only in the last bits of the factors
  * mdls_set_tuning returns 0, -1 for an unknown option, -2 for a value out of range;
  * mdls_get_tuning returns the current value (-1 for an unknown option).
  */
@@ -94,7 +101,8 @@ enum {
     MDLS_TUNE_PANEL_VARIANT = 2,
     MDLS_TUNE_APPLY_GRID_CAP = 3,
     MDLS_TUNE_APPLY_WIDE_ROWS = 4,
-    MDLS_TUNE_SPIN_LIMIT = 5
+    MDLS_TUNE_SPIN_LIMIT = 5,
+    MDLS_TUNE_SPLIT_UPDATE = 6
 };
 int mdls_set_tuning(int option, long value);
 long mdls_get_tuning(int option);
@@ -219,7 +227,7 @@ const char *mdls_status_string(int status);
  * and C is scaled by a power of two, every entry cut into 7 slices of at most 19 bits, and
  * the slice products summed exactly in FP64 by level, then renormalised to double double
  * (normwise error below 2^-104 of max|Y| max|C| h).  Y is h x w (2 planes of ldy x w), C is
- * h x c (2 planes of ldc x c), S is w x c (2 planes of lds x c).  Method 1 needs h <= 1024
+ * h x c (2 planes of ldc x c), S is w x c (2 planes of lds x c).  Method 1 needs h <= 2048
  * (the exactness bound), w <= 16, and a workspace of mdls_dd_gemm_tn_workspace_bytes(w, c)
  * bytes; method 0 needs none (ws may be NULL).  Status -1..-12 for arguments 1..12.
  */

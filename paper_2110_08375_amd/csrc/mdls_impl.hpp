@@ -31,6 +31,7 @@
 #pragma once
 #include "mdls.h"
 #include "mdls_kernels.hpp"
+#include "mdls_split_kernels.hpp"
 
 namespace mdls_impl {
 using namespace mdk;
@@ -1743,6 +1744,7 @@ struct Tuning {
     int apply_grid_cap;    // > 0: workgroups of a concurrent trailing update; 0: the built-in rule
     int apply_wide_rows;   // od: trailing updates of at least this many rows take two workgroups per CU
     unsigned spin_limit;   // polls before a grid barrier gives up
+    int split_update;      // 1: the refined solve's factorisation forms Y^T C on the matrix cores
 };
 Tuning tuning();
 int apply_grid_cap(int P, int h);
@@ -1839,6 +1841,9 @@ struct Ctx {
     char *ws;
     Layout L;
     hipStream_t s;
+    // scratch of the split-limb trailing-update product (double double only), or null: then the
+    // products Y^T C run on the vector units
+    double *split = nullptr;
     double *beta() const { return (double *)(ws + L.beta); }
     double *leafT() const { return (double *)(ws + L.leafT); }
     double *gpart() const { return (double *)(ws + L.gpart); }
@@ -1929,10 +1934,68 @@ int panel_occupancy_t(PanelCfg cf)
 // Householder QR of A (m x n) in narrow panels; B (nb columns, may be null) receives Q^T B.
 // The trailing update (k_apply_s, k_apply_t, k_apply_u) in launches of at most L.acols
 // columns.  Rows per unit: the largest of 256, 128, 64 that still gives two units per CU.
+// Bytes of Ctx::split for factorisations of n columns: the panel's Householder block staged
+// densely (2 planes of kSplitMaxRows x 16), the exact level sums and the column exponents.
+inline size_t split_scratch_bytes(int n)
+{
+    return align256(sizeof(double) * 2 * (size_t)kSplitMaxRows * 16) + split_workspace_bytes(16, n + 1) + 256;
+}
+
+// The trailing update of a double-double panel with S = Y^T C formed exactly on the FP64 matrix
+// cores (k_split_tn; the precision form's split-limb product), then -U = -T^T S and C -= Y U on
+// the vector units as in launch_apply.
+template <int P>
+void launch_apply_split(const Ctx<P> &cx, ApplyArgs aa, int grid_cap, hipStream_t st)
+{
+    constexpr int W = Cfg<P>::W;
+    static_assert(P == 2 && W <= 16, "split-limb products: double double, at most 16 columns of Y");
+    double *Yd = cx.split;
+    double *spart = Yd + 2L * kSplitMaxRows * 16;
+    const size_t spart_bytes = align256(sizeof(double) * (size_t)((cx.L.acols + 15) / 16) * kSplitK * kSlices * 256);
+    int *exps = (int *)((char *)spart + spart_bytes);
+    MDLS_LAUNCH("k_stage_y", P, 0, k_stage_y, dim3((unsigned)(((long)aa.h * W + kThreads - 1) / kThreads)), dim3(kThreads),
+                st, aa.Y, aa.ldy, aa.psy, aa.h, aa.wact, W, Yd);
+    aa.part = cx.apart();
+    aa.nu = cx.anu();
+    for (int c0 = 0; c0 < aa.nc; c0 += cx.L.acols) {
+        aa.c0 = c0;
+        aa.ncol = (aa.nc - c0 < cx.L.acols) ? (aa.nc - c0) : cx.L.acols;
+        SplitArgs sa{Yd, (long)aa.h, (long)aa.h * W, aa.C + (long)c0 * aa.ldc, aa.ldc, aa.psc, spart, exps, aa.h, W,
+                     aa.ncol};
+        const int tiles = (aa.ncol + 15) / 16;
+        MDLS_LAUNCH("k_split_exp", P, 0, k_split_exp, dim3((W + aa.ncol + 3) / 4), dim3(kThreads), st, sa);
+        MDLS_LAUNCH("k_split_tn", P, (double)aa.h * aa.wact * aa.ncol, k_split_tn, dim3(tiles, kSplitK),
+                    dim3(64 * kSplitWaves), st, sa);
+        MDLS_LAUNCH("k_split_fin", P, 0, k_split_fin_part, dim3(tiles), dim3(256), st, sa, aa.part);
+        const int ncg = (aa.ncol + 3) / 4;
+        ApplyArgs at = aa;
+        at.rb = aa.h;
+        at.nrb = 1;  // S is complete: one partial sum per column
+        int tgrid = ncg;
+        if (grid_cap > 0 && tgrid > grid_cap) tgrid = grid_cap;
+        MDLS_LAUNCH("k_apply_t", P, 0.5 * aa.wact * (aa.wact + 1) * aa.ncol, (k_apply_t<P, W>), dim3(tgrid),
+                    dim3(kThreads), st, at);
+        int rb = rb_max<P, W>();
+        while (rb > 64 && (long)ncg * ((aa.h + rb - 1) / rb) < 2L * kCUs) rb >>= 1;
+        aa.rb = rb;
+        aa.nrb = (aa.h + rb - 1) / rb;
+        int grid = ncg * aa.nrb;
+        if (grid_cap > 0 && grid > grid_cap) grid = grid_cap;
+        MDLS_LAUNCH("k_apply_u", P, (double)aa.h * aa.wact * aa.ncol, (k_apply_u<P, W>), dim3(grid), dim3(kThreads), st,
+                    aa);
+    }
+}
+
 template <int P>
 void launch_apply(const Ctx<P> &cx, ApplyArgs aa, int grid_cap, hipStream_t st)
 {
     constexpr int W = Cfg<P>::W;
+    if constexpr (P == 2) {
+        if (cx.split && aa.nb == 0 && aa.h <= kSplitMaxRows) {
+            launch_apply_split<P>(cx, aa, grid_cap, st);
+            return;
+        }
+    }
     const int ntot = aa.nc + aa.nb;
     aa.part = cx.apart();
     aa.nu = cx.anu();
@@ -2156,10 +2219,11 @@ int solve_t(int m, int n, int tile, double *A, int lda, double *b, double *x, vo
 }
 
 template <int P>
-int qr_t(int m, int n, int tile, double *A, int lda, double *beta, double *T, int ldt, void *ws, int *d_info,
-         hipStream_t s)
+int qr_impl(int m, int n, int tile, double *A, int lda, double *beta, double *T, int ldt, void *ws, int *d_info,
+            hipStream_t s, double *split)
 {
     Ctx<P> cx{(char *)ws, layout(P, m, n, tile), s};
+    cx.split = split;
     const long psa = (long)lda * n;
     if (qr_panels<P>(cx, m, n, A, lda, psa, nullptr, 0, 0, 0) != 0) return MDLS_EHIP;
     if (beta)
@@ -2186,6 +2250,21 @@ int qr_t(int m, int n, int tile, double *A, int lda, double *beta, double *T, in
         invert_tiles<P>(cx, ia, N);
     }
     return hipGetLastError() == hipSuccess ? 0 : MDLS_EHIP;
+}
+
+template <int P>
+int qr_t(int m, int n, int tile, double *A, int lda, double *beta, double *T, int ldt, void *ws, int *d_info,
+         hipStream_t s)
+{
+    return qr_impl<P>(m, n, tile, A, lda, beta, T, ldt, ws, d_info, s, nullptr);
+}
+
+// The double-double QR with its trailing-update products Y^T C on the matrix cores (split ->
+// split_scratch_bytes(n) bytes); the refined solve's factorisation.
+template <int P>
+int qr_split_t(int m, int n, int tile, double *A, int lda, double *T, int ldt, void *ws, double *split, hipStream_t s)
+{
+    return qr_impl<P>(m, n, tile, A, lda, nullptr, T, ldt, ws, nullptr, s, split);
 }
 
 // B := Q^T B by the tile blocks in order, B := B - Y_k T_k^T (Y_k^T B), 64 columns of B at a
@@ -2433,7 +2512,7 @@ inline size_t refine_extra_bytes(int px, int m, int n, int tile)
     const size_t nch = (size_t)(n + kResidCols - 1) / kResidCols;
     return sizeof(double) * (2 * (size_t)n * tile + 2 * (size_t)px * m + 2 * (size_t)m + 6 * (size_t)n +
                              nch * px * m + 4 * (size_t)tile * 64) +
-           10 * 256;
+           10 * 256 + split_scratch_bytes(n);
 }
 
 template <int PX>
@@ -2460,6 +2539,7 @@ int refine_t(int m, int n, int tile, const double *A, int lda, const double *b, 
     double *part = (double *)take(sizeof(double) * (size_t)nch * PX * m);
     double *S = (double *)take(sizeof(double) * 4 * (size_t)tile * 64);
     int *done = (int *)take(sizeof(int) * 4);
+    double *split = (double *)take(split_scratch_bytes(n));
     double *U = S + 2 * (size_t)tile * 64;
     const long psa = (long)lda * n;
     const int N = n / tile;
@@ -2471,7 +2551,9 @@ int refine_t(int m, int n, int tile, const double *A, int lda, const double *b, 
         MDLS_LAUNCH("k_zero", PX, 0, k_zero_f64, dim3((2 * n + 255) / 256), dim3(256), s, gdd, 2L * n);
     }
     MDLS_LAUNCH("k_refine_init", PX, 0, k_refine_init, dim3((2 * iters + 255) / 256), dim3(256), s, norms, iters, done);
-    int rc = qr_t<2>(m, n, tile, F, lda, nullptr, T, tile, ws, nullptr, s);
+    // with MDLS_TUNE_SPLIT_UPDATE the factorisation's trailing-update products Y^T C run on the
+    // FP64 matrix cores (split limbs); by default on the vector units
+    int rc = qr_split_t<2>(m, n, tile, F, lda, T, tile, ws, tuning().split_update ? split : nullptr, s);
     if (rc != 0) return rc;
     double *Xinv = cx.big();
     const long xips = (long)tile * n;
@@ -2530,6 +2612,7 @@ int refine_t(int m, int n, int tile, const double *A, int lda, const double *b, 
 #define MDLS_FOR_PRECISION(X, P)                                                                        \
     X template int solve_t<P>(int, int, int, double *, int, double *, double *, void *, int *, hipStream_t);     \
     X template int qr_t<P>(int, int, int, double *, int, double *, double *, int, void *, int *, hipStream_t); \
+    X template int qr_split_t<P>(int, int, int, double *, int, double *, int, void *, double *, hipStream_t); \
     X template int apply_qt_t<P>(int, int, int, const double *, int, const double *, int, double *, int, int,   \
                                  void *, hipStream_t);                                                         \
     X template int form_w_t<P>(int, int, int, const double *, int, const double *, int, double *, int,         \

@@ -152,3 +152,45 @@ def test_refined_full_size_vs_plain(M, orc, P, iters):
                                                     F_ops / (ms[-1] * 1e-3) / 1e12), flush=True)
     assert err <= TOL[P] * max(1.0, kap)
     assert errp <= TOL[P] * max(1.0, kap)
+
+
+@pytest.mark.parametrize("P,m,n,tile", [(4, 640, 384, 64), (8, 1280, 256, 128)])
+def test_refined_split_update_matches_oracle(M, orc, P, m, n, tile):
+    """The option that forms the factorisation's trailing-update products Y^T C on the FP64 matrix
+    cores (exact slicing): the refined solution still matches the oracle's least-squares solution
+    of the stored data (nonzero residual, kappa = 1e8) to the same bound, the matrix-core kernel
+    ran, and the product rows above 1024 (the second case's first panels) take the same path."""
+    print("case refined split update P=%d m=%d n=%d" % (P, m, n), flush=True)
+    A = mdgen.conditioned(2, m, n, 190 + P, kappa=1e8)
+    xt = mdgen.md_vector(P, n, 191, mdgen.STREAM_X)
+    A64 = A[0].T + A[1].T
+    g = mdgen.md_vector(1, m, 192, mdgen.STREAM_B)[0]
+    r = g - A64 @ np.linalg.lstsq(A64, g, rcond=None)[0]
+    t = 1e-6 / np.linalg.norm(r)
+    rv = np.zeros((P, m))
+    rv[0] = t * r
+    b = -orc.matvec(A, xt, P, c=-rv)
+    Ap = np.zeros((P, n, m))
+    Ap[:2] = A
+    ref = orc.lstsq(Ap, b)
+    M.set_tuning(M.MDLS_TUNE_SPLIT_UPDATE, 1)
+    try:
+        M.timing_reset()
+        M.timing_enable(True)
+        x, info, norms = M.solve_refined(P, to_gpu(A), to_gpu(b), tile, 12)
+        torch.cuda.synchronize()
+        M.timing_enable(False)
+        ms, cnt, work = M.timing_query("k_split_tn", 0)
+    finally:
+        M.set_tuning(M.MDLS_TUNE_SPLIT_UPDATE, 0)
+    assert int(info.item()) == 0
+    assert cnt > 0, "the matrix-core product did not run"
+    kap = float(np.linalg.cond(A64))
+    rho = np.linalg.norm(t * r) / (np.linalg.norm(A64, 2) * np.linalg.norm(ref["x"][0]))
+    err = md_err(x.cpu().numpy(), ref["x"])
+    nr = steps_taken(norms)
+    bound = TOL[P] * kap * (1.0 + kap * rho)
+    print("refined split update P=%d err vs oracle %.3e bound %.3e steps %d k_split_tn launches %d"
+          % (P, err, bound, len(nr), cnt), flush=True)
+    assert err <= bound
+    assert len(nr) < 12

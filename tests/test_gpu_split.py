@@ -47,7 +47,7 @@ def check(S, Sx, Y, C, what):
     assert ratio <= 1.0
 
 
-@pytest.mark.parametrize("h,w,c", [(1024, 16, 1008), (333, 5, 37), (4, 16, 16), (1000, 16, 65)])
+@pytest.mark.parametrize("h,w,c", [(1024, 16, 1008), (333, 5, 37), (4, 16, 16), (1000, 16, 65), (2048, 16, 48)])
 def test_split_and_vector_match_exact(M, orc, h, w, c):
     print("case dd_gemm_tn h=%d w=%d c=%d" % (h, w, c), flush=True)
     Y = mdgen.md_uniform(2, h, w, 4100 + h, mdgen.STREAM_A)
@@ -69,6 +69,6 @@ def test_split_zero_column_and_limits(M):
     S = M.dd_gemm_tn(1, torch.from_numpy(Y).to(dev()), torch.from_numpy(C).to(dev()))
     torch.cuda.synchronize()
     assert np.all(S.cpu().numpy()[:, 7, :] == 0.0)
-    big = torch.zeros((2, 1, 1025), dtype=torch.float64, device=dev())
+    big = torch.zeros((2, 1, 2049), dtype=torch.float64, device=dev())
     with pytest.raises(Exception):
         M.dd_gemm_tn(1, big, big)  # h above the exactness bound is refused on the host
