@@ -73,10 +73,11 @@ int mdls_finalize(void);
 
 /*
  * Process-wide tuning, for benchmarks and tests; the defaults are built in and nothing is
- * read from the environment.  Only MDLS_TUNE_PANEL_VARIANT and MDLS_TUNE_SPLIT_UPDATE change
- * results (the panel's workgroup shape and so its reduction order; the rounding of the update
- * products); the others change only speed or, for the spin limit, how long a grid barrier waits
- * before it reports -1 through *d_info.
+ * read from the environment.  Only MDLS_TUNE_PANEL_VARIANT, MDLS_TUNE_SPLIT_UPDATE and
+ * MDLS_TUNE_CPANEL change results (the panel's workgroup shape and so its reduction order; the
+ * rounding of the update products; the complex reflector's formulas); the others change only
+ * speed or, for the spin limit, how long a grid barrier (or the complex panel's wait for the
+ * previous column) polls before it reports -1 through *d_info.
  *   MDLS_TUNE_LOOKAHEAD        1 (default): concurrent trailing update after mdls_init; 0: off
  *   MDLS_TUNE_PANEL_VARIANT    0 (default) or 1: the panel kernel's alternative shape (more rows
  *                              per thread: dd 512 x 8, qd 256 x 4, od 256 x 2 threads x rows);
@@ -93,6 +94,13 @@ int mdls_finalize(void);
  *                              of on the vector units; the products are exactly rounded either
  *                              way up to the vector units' lazy accumulation, so results differ
  *                              only in the last bits of the factors
+ *   MDLS_TUNE_CPANEL           the complex QR's tile panels: 0 one launch per panel column;
+ *                              1 one persistent launch per panel (one workgroup per column, the
+ *                              columns handed on through device memory); 2 (default) persistent
+ *                              for qd and od, a launch per column for double and dd (the faster
+ *                              form of each on MI355X).  The persistent form takes the reflector
+ *                              scalars in another (equivalent) order, so results differ in the
+ *                              last bits
  * mdls_set_tuning returns 0, -1 for an unknown option, -2 for a value out of range;
  * mdls_get_tuning returns the current value (-1 for an unknown option).
  */
@@ -102,7 +110,8 @@ enum {
     MDLS_TUNE_APPLY_GRID_CAP = 3,
     MDLS_TUNE_APPLY_WIDE_ROWS = 4,
     MDLS_TUNE_SPIN_LIMIT = 5,
-    MDLS_TUNE_SPLIT_UPDATE = 6
+    MDLS_TUNE_SPLIT_UPDATE = 6,
+    MDLS_TUNE_CPANEL = 7
 };
 int mdls_set_tuning(int option, long value);
 long mdls_get_tuning(int option);
@@ -260,6 +269,10 @@ size_t mdls_cworkspace_bytes(int p, int m, int n, int tile);
  * the workspace.  T (may be NULL; 2P planes of ldt x n, ldt >= tile) receives for each tile
  * block k the upper-triangular T_k with H_{k*tile} ... H_{k*tile+tile-1} = I - Y_k T_k Y_k^H
  * (diag(T_k) = beta); the paper's W is W_k = -Y_k T_k.  Status -1..-10 for arguments 1..10.
+ * A tile panel is one persistent launch (where MDLS_TUNE_CPANEL selects it) while its column
+ * fits in 64 KiB of LDS (m - k*tile rows <= 4096/p) and its tile workgroups can all be
+ * resident; a column waits for the one before it with a bounded poll: should a wait time out
+ * (MDLS_TUNE_SPIN_LIMIT), R(0,0) is set to NaN here and mdls_csolve reports *d_info = -1.
  */
 int mdls_cqr(int p, int m, int n, int tile, double *A, int lda, double *T, int ldt, void *ws,
              size_t ws_bytes, hipStream_t stream);

@@ -75,6 +75,7 @@ std::atomic<int> g_apply_grid_cap{0};
 std::atomic<int> g_apply_wide_rows{768};
 std::atomic<unsigned> g_spin_limit{1u << 22};
 std::atomic<int> g_split_update{0};
+std::atomic<int> g_cpanel{2};
 
 // occupancy-derived capacity of the panel kernel, per (device, precision index, variant)
 std::atomic<int> g_capacity[kMaxDev][4][2];
@@ -99,6 +100,7 @@ Tuning tuning()
     t.apply_wide_rows = g_apply_wide_rows.load(std::memory_order_relaxed);
     t.spin_limit = g_spin_limit.load(std::memory_order_relaxed);
     t.split_update = g_split_update.load(std::memory_order_relaxed);
+    t.cpanel = g_cpanel.load(std::memory_order_relaxed);
     return t;
 }
 
@@ -782,6 +784,10 @@ int mdls_set_tuning(int option, long value)
         if (value != 0 && value != 1) return -2;
         g_split_update.store((int)value);
         return 0;
+    case MDLS_TUNE_CPANEL:
+        if (value < 0 || value > 2) return -2;
+        g_cpanel.store((int)value);
+        return 0;
     }
     return -1;
 }
@@ -796,6 +802,7 @@ long mdls_get_tuning(int option)
     case MDLS_TUNE_APPLY_WIDE_ROWS: return t.apply_wide_rows;
     case MDLS_TUNE_SPIN_LIMIT: return (long)t.spin_limit;
     case MDLS_TUNE_SPLIT_UPDATE: return t.split_update;
+    case MDLS_TUNE_CPANEL: return t.cpanel;
     }
     return -1;
 }

@@ -30,6 +30,8 @@
 //   k_cbs_xi, k_cbs_upd -- x_i := U_i^{-1} b_i and b_j -= A_{j,i} x_i;
 //   k_ctrmm_n, k_cidentity -- Q B and the explicit unitary factor (the blocks in reverse).
 #pragma once
+#include <atomic>
+
 #include "mdls_impl.hpp"
 
 namespace mdls_impl {
@@ -403,6 +405,354 @@ __global__ __launch_bounds__(kThreads) void k_cstep_r(CPanelArgs g)
     }
 }
 
+// ============================================================================ persistent panel
+// One launch per tile panel (columns kt .. kt + tile - 1, rows kt .. m - 1): workgroup b owns
+// column c = kt + b for the whole launch, its h = m - kt rows held in LDS (2P planes of h
+// doubles).  For j = kt .. c - 1 it waits until column j is published and applies H_j to its
+// column; then it publishes its own column and last writes the column's final values.
+//
+// What is published for column j is the column x itself (rows below the diagonal, staged in
+// a workspace buffer) and three scalars, not v = x/v1: with iv = 1/v1 and D = sum_{i>j}
+// conj(x_i) a_i, H_j a has w = v^H a = a_j + conj(iv) D, row j becomes a_j - beta w =
+// (1 - beta) a_j + conj(p1) D and the rows below a_i + x_i (p1 a_j + p2 D), where p1 =
+// -beta iv and p2 = -beta |iv|^2.  The owner stages x before its reflector's chain (the stores
+// overlap it), then stores p1, p2, beta, fences (release) and sets *count = c + 1; scaling its
+// rows to v waits until the end, and so does the update of row j by H_j (D is kept in the
+// unused head of the column's own staging slot), so neither is on the chain.  A workgroup
+// waits only for lower-numbered ones and each wait is a bounded poll (a time-out raises *err,
+// after which no wait polls), so the grid always drains.
+//
+// The reflector (the same vector as c_reflector's) is formed with a short chain: the four long
+// md operations sqrt(q), 1/q, 1/sqrt(|x1|^2) and 1/sigma (q = |x1|^2 + sigma) run side by side,
+// one per wave, and the rest are products: with rho = |x1|, mu = sqrt(q), nu = -sigma/(rho + mu)
+// and v1 = e^{i theta} nu, 1/v1 = -conj(x1) (rho + mu)/(rho sigma), R_cc = x1 mu/rho, and
+// beta = 2 nu^2/(sigma + nu^2) = sigma/(mu (mu + rho)) = 1 - rho/mu; the last form is used while
+// sigma >= |x1|^2 (then rho/mu <= 1/sqrt 2, no cancellation), the one before it otherwise.
+// x1 = 0 gives v1 = -mu, beta = 1, R_cc = mu.
+struct CPersistArgs {
+    double *A;  // whole matrix, 2P planes of stride ps, leading dimension lda
+    long lda, ps;
+    int m, kt;
+    double *beta;  // P planes of stride bps
+    long bps;
+    double *xs;    // staged columns: 2P planes of stride xps, panel column b at b * m
+    long xps;
+    double *rec;   // per column c: p1 (2P doubles), p2, beta (P each) at rec + 4P c
+    unsigned *count;  // columns published in this factorisation; zero before its first panel
+    int *err;         // set to 1 if a wait times out
+    unsigned spin;    // polls before a wait gives up
+};
+
+// Largest panel height of k_cpanel<P>: the column's 2P planes fit in 64 KiB of LDS.
+template <int P>
+constexpr int kCPanelRows = 4096 / P;
+
+// Butterfly sum of a lazy accumulator over the 64 lanes, renormalised every kLazy<P> terms;
+// both operands of each addition enter symmetrically, so every lane ends with the same bits.
+template <int P>
+__device__ __forceinline__ V<P> acc_wave_total(Acc<P> t)
+{
+    constexpr int RL = (kLazy<P> >= 64) ? 6 : (kLazy<P> >= 16 ? 4 : 2);  // levels per renormalisation
+#pragma unroll
+    for (int lv = 0; lv < 6; ++lv) {
+        acc_add_acc(t, shfl_xor_acc(t, 32 >> lv));
+        if ((lv + 1) % RL == 0 && lv < 5) t = acc_from(acc_get(t));
+    }
+    return acc_get(t);
+}
+
+// Workgroup totals, the same bits in every thread (the wave totals added in a fixed order);
+// sred holds (kThreads / 64) * 2P doubles.  Called by all threads.
+template <int P>
+__device__ __forceinline__ CV<P> cacc_block_total(const CAcc<P> &a, double *sred)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const CV<P> w{acc_wave_total(a.re), acc_wave_total(a.im)};
+    if (lane == 0) clds_st(&sred[wid * 2 * P], w);
+    __syncthreads();
+    CAcc<P> t = cacc_zero<P>();
+    for (int k = 0; k < kThreads / 64; ++k) {
+        const CV<P> o = clds_ld<P>(&sred[k * 2 * P]);
+        acc_add(t.re, o.re);
+        acc_add(t.im, o.im);
+    }
+    __syncthreads();
+    return cacc_get(t);
+}
+
+template <int P>
+__device__ __forceinline__ V<P> acc_block_total(const Acc<P> &a, double *sred)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const V<P> w = acc_wave_total(a);
+    if (lane == 0) lds_st(&sred[wid * P], w);
+    __syncthreads();
+    Acc<P> t = acc_zero<P>();
+    for (int k = 0; k < kThreads / 64; ++k) acc_add(t, lds_ld<P>(&sred[k * P]));
+    __syncthreads();
+    return acc_get(t);
+}
+
+template <int P>
+__device__ __forceinline__ CV<P> cld_coherent(const double *X, long ps, long off)
+{
+    CV<P> v;
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        v.re.x[k] = ld_coherent(X + k * ps + off);
+        v.im.x[k] = ld_coherent(X + (P + k) * ps + off);
+    }
+    return v;
+}
+
+template <int P>
+__device__ __forceinline__ void cst_coherent(double *X, long ps, long off, const CV<P> &v)
+{
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        st_coherent(X + k * ps + off, v.re.x[k]);
+        st_coherent(X + (P + k) * ps + off, v.im.x[k]);
+    }
+}
+
+// Wait until *count >= target: thread 0 polls (each poll after a short sleep), giving up after
+// spin polls or once *err is set, then acquires; the barrier passes that on to the other
+// threads, whose reads of published data are coherent loads.  Called by all threads.
+__device__ inline void wait_count(unsigned *count, unsigned target, int *err, unsigned spin)
+{
+    if (threadIdx.x == 0) {
+        unsigned spins = 0;
+        while (__hip_atomic_load(count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if ((spins & 255u) == 255u && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > spin) {
+                __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+}
+
+template <int P>
+__global__ __launch_bounds__(kThreads) void k_cpanel(CPersistArgs g)
+{
+    constexpr int QM = kCPanelRows<P> / kThreads;  // rows per thread
+    extern __shared__ double sCol[];              // plane p of the column at sCol + p h
+    __shared__ double sred[(kThreads / 64) * 2 * P];
+    __shared__ double sch[4 * P];                 // sqrt(q), 1/q, 1/rho, 1/sigma
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int h = g.m - g.kt;
+    const int jc = blockIdx.x;  // the column's diagonal row, counted from row kt
+    const int c = g.kt + jc;
+    const long offc = (long)c * g.lda + g.kt;
+    double *const xc = g.xs + (long)jc * g.m;  // the column's staging slot
+    // thread t holds rows t + q kThreads of the column (in LDS; other threads read only row
+    // jj of step j and row jc, after the reductions that follow their last writes)
+    auto sld = [&](int i) __attribute__((always_inline)) {
+        CV<P> v;
+#pragma unroll
+        for (int e = 0; e < P; ++e) {
+            v.re.x[e] = sCol[(long)e * h + i];
+            v.im.x[e] = sCol[(long)(P + e) * h + i];
+        }
+        return v;
+    };
+    auto sst = [&](int i, const CV<P> &v) __attribute__((always_inline)) {
+#pragma unroll
+        for (int e = 0; e < P; ++e) {
+            sCol[(long)e * h + i] = v.re.x[e];
+            sCol[(long)(P + e) * h + i] = v.im.x[e];
+        }
+    };
+#pragma unroll
+    for (int q = 0; q < QM; ++q) {
+        const int i = tid + q * kThreads;
+        if (i < h) sst(i, cldm<P>(g.A, g.ps, offc + i));
+    }
+
+    // ---- H_j for the columns before c; row jj keeps its value, D goes to the staging slot
+    for (int j = g.kt; j < c; ++j) {
+        const int jj = j - g.kt;
+        wait_count(g.count, (unsigned)(j + 1), g.err, g.spin);
+        const double *rj = g.rec + (long)4 * P * j;
+        const double *xj = g.xs + (long)jj * g.m;
+        // the staged column and the scalars together (one round trip)
+        CV<P> x[QM];
+#pragma unroll
+        for (int q = 0; q < QM; ++q) {
+            const int i = tid + q * kThreads;
+            x[q] = (i > jj && i < h) ? cld_coherent<P>(xj, g.xps, i) : czero<P>();
+        }
+        CV<P> p1;
+        V<P> p2, bt;
+#pragma unroll
+        for (int e = 0; e < P; ++e) {
+            p1.re.x[e] = ld_coherent(rj + e);
+            p1.im.x[e] = ld_coherent(rj + P + e);
+            p2.x[e] = ld_coherent(rj + 2 * P + e);
+            bt.x[e] = ld_coherent(rj + 3 * P + e);
+        }
+        if (is_zero(bt)) continue;  // identity reflector (uniform)
+        const CV<P> st1 = cmul(p1, sld(jj));  // p1 a_j, beside the dot
+        // D: at most 2 QM = 32/P products per part, within kLazy<P>, renormalised at the end
+        CAcc<P> acc = cacc_zero<P>();
+#pragma unroll
+        for (int q = 0; q < QM; ++q) {
+            const int i = tid + q * kThreads;
+            if (i > jj && i < h) cacc_fma<P, true>(acc, x[q], sld(i));
+        }
+        const CV<P> D = cacc_block_total(cacc_from(cacc_get(acc)), sred);
+        CAcc<P> t = cacc_from(st1);
+        acc_fma(t.re, p2, D.re);
+        acc_fma(t.im, p2, D.im);
+        const CV<P> sc = cacc_get(t);  // p1 a_j + p2 D
+#pragma unroll
+        for (int q = 0; q < QM; ++q) {
+            const int i = tid + q * kThreads;
+            if (i > jj && i < h) {
+                CAcc<P> u = cacc_from(sld(i));
+                cacc_fma<P, false>(u, x[q], sc);
+                sst(i, cacc_get(u));
+            }
+        }
+        if (tid == (jj & (kThreads - 1))) cstm(xc, g.xps, jj, D);
+    }
+
+    // ---- stage the column below the diagonal, form the reflector, publish
+    Acc<P> sacc = acc_zero<P>();
+#pragma unroll
+    for (int q = 0; q < QM; ++q) {
+        const int i = tid + q * kThreads;
+        if (i > jc && i < h) {
+            const CV<P> x = sld(i);
+            cst_coherent(xc, g.xps, i, x);
+            acc_fma(sacc, x.re, x.re);
+            acc_fma(sacc, x.im, x.im);
+        }
+    }
+    const V<P> sig = acc_block_total(acc_from(acc_get(sacc)), sred);  // its barriers publish row jc
+    const CV<P> x1 = sld(jc);
+    const bool ident = is_zero(sig);  // identity reflector: beta = 0, R_cc = x1
+    CV<P> iv = cone<P>(), rjj = x1, p1 = czero<P>();  // iv: the factor of the rows below
+    V<P> bt = zero<P>(), p2 = zero<P>();
+    if (!ident) {
+        const V<P> a2 = cabs2(x1);
+        const V<P> q = add(a2, sig);
+        const bool x1z = is_zero(a2);
+        {
+            V<P> r;
+            if (wid == 0)
+                r = sqrt_md(q);
+            else if (wid == 1)
+                r = recip(q);
+            else if (wid == 2)
+                r = x1z ? zero<P>() : rsqrt(a2);
+            else
+                r = recip(sig);
+            if (lane == 0) lds_st(&sch[(wid & 3) * P], r);
+        }
+        __syncthreads();
+        const V<P> mu = lds_ld<P>(&sch[0]), iq = lds_ld<P>(&sch[P]), ir = lds_ld<P>(&sch[2 * P]),
+                   is = lds_ld<P>(&sch[3 * P]);
+        if (x1z) {
+            const V<P> imu = mul(mu, iq);
+            iv = CV<P>{neg(imu), zero<P>()};
+            bt = from_double<P>(1.0);
+            rjj = CV<P>{mu, zero<P>()};
+            p1 = CV<P>{imu, zero<P>()};
+            p2 = neg(iq);
+        } else {
+            const V<P> rho = mul(a2, ir);
+            const V<P> u = mul(add(rho, mu), mul(ir, is));  // (rho + mu)/(rho sigma)
+            iv = CV<P>{neg(mul(x1.re, u)), mul(x1.im, u)};
+            const V<P> mir = mul(mu, ir);
+            rjj = CV<P>{mul(x1.re, mir), mul(x1.im, mir)};
+            if (sub(sig, a2).x[0] >= 0.0)
+                bt = fma(from_double<P>(1.0), neg(rho), mul(mu, iq));
+            else
+                bt = mul(sig, recip(mul(mu, add(mu, rho))));
+            const V<P> nb = neg(bt);
+            p1 = cscale(iv, nb);
+            p2 = mul(nb, cabs2(iv));
+        }
+    }
+    if (tid == 0) {
+        double *rc = g.rec + (long)4 * P * c;
+#pragma unroll
+        for (int e = 0; e < P; ++e) {
+            st_coherent(rc + e, p1.re.x[e]);
+            st_coherent(rc + P + e, p1.im.x[e]);
+            st_coherent(rc + 2 * P + e, p2.x[e]);
+            st_coherent(rc + 3 * P + e, bt.x[e]);
+        }
+        stm(g.beta, g.bps, c, bt);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (tid == 0) __hip_atomic_store(g.count, (unsigned)(c + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+
+    // ---- final values (read only by later launches): row j of step j, R_cc, v = x/v1 below
+#pragma unroll
+    for (int q = 0; q < QM; ++q) {
+        const int i = tid + q * kThreads;
+        if (i < jc) {  // (1 - beta) a_j + conj(p1) D of step j = kt + i
+            const double *rj = g.rec + (long)4 * P * (g.kt + i);
+            CV<P> pj;
+            V<P> bj;
+#pragma unroll
+            for (int e = 0; e < P; ++e) {
+                pj.re.x[e] = ld_coherent(rj + e);
+                pj.im.x[e] = ld_coherent(rj + P + e);
+                bj.x[e] = ld_coherent(rj + 3 * P + e);
+            }
+            CV<P> a = sld(i);
+            if (!is_zero(bj)) {
+                CAcc<P> t = cacc_from(a);
+                const V<P> nb = neg(bj);
+                acc_fma(t.re, nb, a.re);
+                acc_fma(t.im, nb, a.im);
+                cacc_fma<P, true>(t, pj, cldm<P>(xc, g.xps, i));
+                a = cacc_get(t);
+            }
+            cstm(g.A, g.ps, offc + i, a);
+        } else if (i == jc) {
+            cstm(g.A, g.ps, offc + i, rjj);
+        } else if (i < h) {
+            cstm(g.A, g.ps, offc + i, cmul(sld(i), iv));
+        }
+    }
+}
+
+namespace {
+// A wait of the persistent panel timed out: R(0, 0) := NaN, so that the failure shows.
+__global__ void k_cpoison(const int *err, double *A)
+{
+    if (threadIdx.x == 0 && *err != 0) A[0] = __builtin_nan("");
+}
+}  // namespace
+
+// Workgroups of k_cpanel<P> one device can hold at once (with the largest column, 64 KiB of
+// LDS), cached per device; 0 if the device cannot be queried.
+template <int P>
+int cpanel_capacity()
+{
+    static std::atomic<int> cache[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+    int c = cache[dev].load(std::memory_order_relaxed);
+    if (c > 0) return c;
+    int cus = 0, per_cu = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cpanel<P>, kThreads,
+                                                     (size_t)kCPanelRows<P> * 2 * P * sizeof(double)) != hipSuccess)
+        return 0;
+    c = cus * per_cu;
+    if (c > 0) cache[dev].store(c, std::memory_order_relaxed);
+    return c;
+}
+
 // G(l, j) = y_l^H y_j for l < j (zero for l >= j) of the block Y (h rows, tile columns);
 // one wave per (l, j): workgroup (lb, j) holds l = lb * 4 .. lb * 4 + 3.
 template <int P>
@@ -615,7 +965,8 @@ template <int P>
 constexpr int kCInvCols = 1;
 
 struct CLayout {
-    size_t beta, T, G, S, U, y, total;
+    size_t beta, T, G, S, U, y, ctr, px, pr, total;  // ctr, px, pr: the persistent panel's count and
+                                                     // error flag, staged columns, scalars
     int sc;  // columns of S and U
 };
 
@@ -636,6 +987,9 @@ inline CLayout clayout(int P, int m, int n, int tile)
     L.S = take(sizeof(double) * 2 * (size_t)P * tile * L.sc);
     L.U = take(sizeof(double) * 2 * (size_t)P * tile * L.sc);
     L.y = take(sizeof(double) * 2 * (size_t)P * (m > n ? m : n));
+    L.ctr = take(sizeof(unsigned) * 2);
+    L.px = take(sizeof(double) * 2 * (size_t)P * m * tile);
+    L.pr = take(sizeof(double) * 4 * (size_t)P * n);
     L.total = off;
     return L;
 }
@@ -664,6 +1018,37 @@ void cblock_apply_h(const double *Y, long lda, long psa, int h, int tile, const 
                 dim3(kThreads), s, Y, lda, psa, h, tile, U, sps, B, ldb, bps);
 }
 
+// The panel's columns kt .. jend - 1 a launch at a time: the first column's reflector, then per
+// column j the update of the columns right of it and the next column's reflector.
+template <int P>
+void cpanel_columns(CPanelArgs pa, int kt, int jend, hipStream_t s)
+{
+    const int m = pa.m;
+    pa.j = kt;
+    pa.jend = jend;
+    MDLS_LAUNCH("k_crefl", P, 6.0 * (m - kt), (k_crefl<P>), dim3(1), dim3(kThreads), s, pa);
+    for (int j = kt; j < jend - 1; ++j) {
+        pa.j = j;
+        const int hj = m - j;
+        const double work = 8.0 * hj * (jend - j - 1) + 6.0 * (hj - 1);
+        const dim3 grid(jend - j - 1);
+        // register-resident rows where they fit without spilling (P <= 4)
+        bool done = false;
+        if constexpr (P <= 4) {
+            done = true;
+            if (hj <= kThreads)
+                MDLS_LAUNCH("k_cstep", P, work, (k_cstep_r<P, 1>), grid, dim3(kThreads), s, pa);
+            else if (hj <= 2 * kThreads)
+                MDLS_LAUNCH("k_cstep", P, work, (k_cstep_r<P, 2>), grid, dim3(kThreads), s, pa);
+            else if (hj <= 4 * kThreads)
+                MDLS_LAUNCH("k_cstep", P, work, (k_cstep_r<P, 4>), grid, dim3(kThreads), s, pa);
+            else
+                done = false;
+        }
+        if (!done) MDLS_LAUNCH("k_cstep", P, work, (k_cstep<P>), grid, dim3(kThreads), s, pa);
+    }
+}
+
 // Blocked complex Householder QR; T (2P planes of ldt x n) receives T_k for every tile block.
 template <int P>
 int cqr_t(int m, int n, int tile, double *A, int lda, double *T, int ldt, void *ws, hipStream_t s)
@@ -680,33 +1065,31 @@ int cqr_t(int m, int n, int tile, double *A, int lda, double *T, int ldt, void *
     }
     const long psa = (long)lda * n, tps = (long)ldt * n, gps = (long)tile * tile, sps = (long)tile * L.sc;
     const int N = n / tile;
-    CPanelArgs pa{A, (long)lda, psa, m, 0, 0, beta, (long)n};
+    const CPanelArgs pa{A, (long)lda, psa, m, 0, 0, beta, (long)n};
+    unsigned *count = (unsigned *)(w + L.ctr);
+    int *err = (int *)(count + 1);
+    // each panel as one persistent launch (the default for qd and od, where it is the faster
+    // form; measured on MI355X: dd and double are faster a launch per column) while its column
+    // fits and its workgroups can all be resident, else a launch per column
+    const Tuning tu = tuning();
+    const bool use = tu.cpanel == 1 || (tu.cpanel == 2 && P >= 4);
+    const bool fits = use && cpanel_capacity<P>() >= tile;
+    MDLS_LAUNCH("k_zero", P, 0, k_zero_u32, dim3(1), dim3(64), s, count, 2);
+    bool persisted = false;
     for (int k = 0; k < N; ++k) {
         const int kt = k * tile, jend = kt + tile;
         const int h = m - kt;
-        pa.j = kt;
-        pa.jend = jend;
-        MDLS_LAUNCH("k_crefl", P, 6.0 * h, (k_crefl<P>), dim3(1), dim3(kThreads), s, pa);
-        for (int j = kt; j < jend - 1; ++j) {
-            pa.j = j;
-            const int hj = m - j;
-            const double work = 8.0 * hj * (jend - j - 1) + 6.0 * (hj - 1);
-            const dim3 grid(jend - j - 1);
-            // register-resident rows where they fit without spilling (P <= 4)
-            bool done = false;
-            if constexpr (P <= 4) {
-                done = true;
-                if (hj <= kThreads)
-                    MDLS_LAUNCH("k_cstep", P, work, (k_cstep_r<P, 1>), grid, dim3(kThreads), s, pa);
-                else if (hj <= 2 * kThreads)
-                    MDLS_LAUNCH("k_cstep", P, work, (k_cstep_r<P, 2>), grid, dim3(kThreads), s, pa);
-                else if (hj <= 4 * kThreads)
-                    MDLS_LAUNCH("k_cstep", P, work, (k_cstep_r<P, 4>), grid, dim3(kThreads), s, pa);
-                else
-                    done = false;
-            }
-            if (!done) MDLS_LAUNCH("k_cstep", P, work, (k_cstep<P>), grid, dim3(kThreads), s, pa);
+        const bool done = fits && h <= kCPanelRows<P>;
+        if (done) {
+            const CPersistArgs ca{A, (long)lda, psa, m, kt, beta, (long)n, (double *)(w + L.px), (long)m * tile,
+                                  (double *)(w + L.pr), count, err, tu.spin_limit};
+            double work = 0;
+            for (int j = 0; j < tile; ++j) work += 8.0 * (h - j) * (tile - j - 1) + 6.0 * (h - j);
+            MDLS_LAUNCH_SHM("k_cpanel", P, work, (k_cpanel<P>), dim3(tile), dim3(kThreads),
+                            (size_t)h * 2 * P * sizeof(double), s, ca);
         }
+        if (!done) cpanel_columns<P>(pa, kt, jend, s);
+        persisted = persisted || done;
         const double *Y = A + (long)kt * lda + kt;
         MDLS_LAUNCH("k_cgram", P, 2.0 * h * tile * tile, (k_cgram<P>), dim3((tile + 3) / 4, tile), dim3(kThreads), s, Y,
                     (long)lda, psa, h, tile, G, gps);
@@ -727,6 +1110,7 @@ int cqr_t(int m, int n, int tile, double *A, int lda, double *T, int ldt, void *
             cblock_apply_h<P>(Y, (long)lda, psa, h, tile, T + (long)kt * ldt, (long)ldt, tps, A + (long)jend * lda + kt,
                               (long)lda, psa, n - jend, S, U, sps, s);
     }
+    if (persisted) MDLS_LAUNCH("k_cpoison", P, 0, k_cpoison, dim3(1), dim3(64), s, err, A);
     return hipGetLastError() == hipSuccess ? 0 : MDLS_EHIP;
 }
 
@@ -853,6 +1237,8 @@ int csolve_t(int m, int n, int tile, double *A, int lda, double *b, double *x, v
     double *y = (double *)(w + L.y);
     MDLS_LAUNCH("k_copy", P, 0, k_copy, dim3((n + 255) / 256), dim3(256), s, b, (long)m, y, (long)n, n, 2 * P);
     cbacksub_tiles<P>(L, w, n, tile, A, lda, (long)lda * n, y, x, n, d_info, s);
+    // a timed-out wait of a persistent panel (cqr_t clears the flag first)
+    MDLS_LAUNCH("k_fold_err", P, 0, k_fold_err, dim3(1), dim3(64), s, (const int *)(w + L.ctr) + 1, d_info);
     return hipGetLastError() == hipSuccess ? 0 : MDLS_EHIP;
 }
 

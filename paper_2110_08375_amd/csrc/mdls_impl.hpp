@@ -1745,6 +1745,7 @@ struct Tuning {
     int apply_wide_rows;   // od: trailing updates of at least this many rows take two workgroups per CU
     unsigned spin_limit;   // polls before a grid barrier gives up
     int split_update;      // 1: the refined solve's factorisation forms Y^T C on the matrix cores
+    int cpanel;            // complex QR panels: 0 a launch per column, 1 persistent, 2 persistent for qd and od
 };
 Tuning tuning();
 int apply_grid_cap(int P, int h);
@@ -1758,6 +1759,16 @@ int panel_capacity(int P, int m);
         const bool tm_ = timing_on();                                                        \
         if (tm_) timing_begin((STREAM), &ev_);                                               \
         hipLaunchKernelGGL(KERNEL, GRID, BLOCK, 0, STREAM, __VA_ARGS__);                     \
+        if (tm_) timing_end((STREAM), ev_, (NAME), (PREC), (double)(WORK));                  \
+    } while (0)
+
+// the same with SHM bytes of dynamic LDS
+#define MDLS_LAUNCH_SHM(NAME, PREC, WORK, KERNEL, GRID, BLOCK, SHM, STREAM, ...)              \
+    do {                                                                                     \
+        void *ev_ = nullptr;                                                                 \
+        const bool tm_ = timing_on();                                                        \
+        if (tm_) timing_begin((STREAM), &ev_);                                               \
+        hipLaunchKernelGGL(KERNEL, GRID, BLOCK, (SHM), STREAM, __VA_ARGS__);                 \
         if (tm_) timing_end((STREAM), ev_, (NAME), (PREC), (double)(WORK));                  \
     } while (0)
 

@@ -19,6 +19,7 @@ MDLS_EHIP, MDLS_EUNSUPPORTED, MDLS_ESCRATCH = -100, -101, -102
 MDLS_NOALLOC_SCRATCH_BYTES = 64 << 20
 MDLS_TUNE_LOOKAHEAD, MDLS_TUNE_PANEL_VARIANT, MDLS_TUNE_APPLY_GRID_CAP = 1, 2, 3
 MDLS_TUNE_APPLY_WIDE_ROWS, MDLS_TUNE_SPIN_LIMIT, MDLS_TUNE_SPLIT_UPDATE = 4, 5, 6
+MDLS_TUNE_CPANEL = 7
 
 # every symbol include/mdls.h declares
 EXPORTS = ("mdls_init", "mdls_finalize", "mdls_set_tuning", "mdls_get_tuning", "mdls_max_rows", "mdls_workspace_bytes", "mdls_qr", "mdls_apply_qt", "mdls_form_w",

@@ -108,6 +108,8 @@ def test_tuning_options(L):
     assert L.mdls_get_tuning(mdls.MDLS_TUNE_LOOKAHEAD) == 1
     assert L.mdls_get_tuning(mdls.MDLS_TUNE_PANEL_VARIANT) == 0
     assert L.mdls_get_tuning(mdls.MDLS_TUNE_SPIN_LIMIT) == 1 << 22
+    assert L.mdls_get_tuning(mdls.MDLS_TUNE_CPANEL) == 2
+    assert L.mdls_set_tuning(mdls.MDLS_TUNE_CPANEL, 3) == -2
     assert L.mdls_get_tuning(99) == -1
     assert L.mdls_set_tuning(99, 0) == -1
     assert L.mdls_set_tuning(mdls.MDLS_TUNE_PANEL_VARIANT, 2) == -2

@@ -87,12 +87,78 @@ CASES = [
     (4, 70, 70, 14),
     (8, 64, 48, 16),
     (8, 33, 20, 10),
+    (8, 544, 64, 32),    # octo double: the first panel taller than the persistent panel's LDS column
     (1, 128, 96, 32),
 ]
 
 
+@pytest.fixture
+def tuning(M):
+    """set_tuning, with the complex panel form and the spin limit restored afterwards"""
+    from paper_2110_08375_amd import mdls
+
+    opts = (mdls.MDLS_TUNE_CPANEL, mdls.MDLS_TUNE_SPIN_LIMIT)
+    saved = {o: M.get_tuning(o) for o in opts}
+    yield M.set_tuning
+    torch.cuda.synchronize()
+    for o, v in saved.items():
+        M.set_tuning(o, v)
+
+
 @pytest.mark.parametrize("P,m,n,tile", CASES)
 def test_csolve_matches_oracle(M, orc, P, m, n, tile):
+    check_csolve(M, orc, P, m, n, tile)
+
+
+@pytest.mark.parametrize("P,m,n,tile", [(2, 128, 128, 32), (2, 700, 40, 8), (4, 96, 64, 16), (8, 64, 48, 16)])
+def test_csolve_per_column_panels(M, orc, tuning, P, m, n, tile):
+    """The panel as one launch per column (the default for double and dd, and the form for
+    columns taller than the persistent panel's LDS column) against the oracle."""
+    from paper_2110_08375_amd import mdls
+
+    tuning(mdls.MDLS_TUNE_CPANEL, 0)
+    check_csolve(M, orc, P, m, n, tile)
+
+
+@pytest.mark.parametrize("P,m,n,tile", [(2, 128, 128, 32), (2, 200, 96, 32), (2, 300, 64, 16), (2, 700, 40, 8),
+                                        (2, 40, 24, 8), (1, 128, 96, 32), (4, 1100, 32, 16)])
+def test_csolve_persistent_panels(M, orc, tuning, P, m, n, tile):
+    """The persistent panel forced for every precision (its default is qd and od only) against
+    the oracle, including sigma = 0 columns, ragged row counts and, for qd at 1100 rows, the
+    first panel left to the per-column form."""
+    from paper_2110_08375_amd import mdls
+
+    tuning(mdls.MDLS_TUNE_CPANEL, 1)
+    check_csolve(M, orc, P, m, n, tile)
+
+
+def test_cpanel_wait_timeout(M, orc, tuning):
+    """A persistent panel whose waits give up at once (spin limit 0, forced from the host:
+    every kernel still ends): csolve reports info = -1 and cqr leaves R(0,0) = NaN; with the
+    default limit the same calls succeed."""
+    from paper_2110_08375_amd import mdls
+
+    P, m, n, tile = 8, 64, 64, 64
+    print("case cpanel timeout P=%d m=%d n=%d tile=%d" % (P, m, n, tile), flush=True)
+    A, _ = mdgen.cls_problem(P, m, n, 3800)
+    b = mdgen.cmd_vector(P, m, 3800, mdgen.STREAM_B)
+    tuning(mdls.MDLS_TUNE_CPANEL, 1)
+    tuning(mdls.MDLS_TUNE_SPIN_LIMIT, 0)
+    x, info = M.csolve(P, to_gpu(A), to_gpu(b), tile)
+    torch.cuda.synchronize()
+    assert int(info.item()) == -1
+    Ag = to_gpu(A)
+    M.cqr(P, Ag, tile)
+    torch.cuda.synchronize()
+    assert np.isnan(Ag.cpu().numpy()[0, 0, 0, 0])
+    tuning(mdls.MDLS_TUNE_SPIN_LIMIT, 1 << 22)
+    x, info = M.csolve(P, to_gpu(A), to_gpu(b), tile)
+    torch.cuda.synchronize()
+    assert int(info.item()) == 0
+    assert np.all(np.isfinite(x.cpu().numpy()))
+
+
+def check_csolve(M, orc, P, m, n, tile):
     print("case csolve P=%d m=%d n=%d tile=%d" % (P, m, n, tile), flush=True)
     A, _ = mdgen.cls_problem(P, m, n, 3000 + m + n)
     b = mdgen.cmd_vector(P, m, 3000 + m + n, mdgen.STREAM_B)
