@@ -824,7 +824,10 @@ __global__ __launch_bounds__(kThreads) void k_cinvert(InvArgs g)
             CV<P> xv = czero<P>();
 #pragma unroll
             for (int q = 0; q < RPT; ++q)
-                if (q == qi) xv = cmul(r[q], clds_ld<P>(&sD[i * Q]));
+                if (q == qi) {
+                    const CV<P> d = clds_ld<P>(&sD[i * Q]);
+                    xv = g.dsup ? cscale(r[q], d.re) : cmul(r[q], d);  // a supplied diagonal is real
+                }
             clds_st(&sX[buf][jl * Q], xv);
             cstm(X, g.psx, (long)j * g.ldx + i, xv);
         }
@@ -839,6 +842,104 @@ __global__ __launch_bounds__(kThreads) void k_cinvert(InvArgs g)
         }
         // sU[buf ^ 1] was last read in step i + 1, before this step's barrier
         if (pre) clds_st(&sU[buf ^ 1][tid * Q], unext);
+    }
+}
+
+// Blocked complex inversion (tiles of 64 columns or more, a multiple of kInvNB = 32), as the
+// real k_inv_blocks: with the 32 x 32 diagonal blocks X_II = U_II^{-1} of every tile formed
+// first (k_cinvert on 32-column tiles: 32 dependent row steps instead of one per row of the
+// tile), the blocks above them follow by block rows from the bottom, X_IK = -X_II sum_{I < J <=
+// K} U_IJ X_JK.  Workgroup (slice, K - 1, tile) forms block column K for NCB of its columns;
+// thread (r, c, p) holds row r and column c of the block row being formed and sums every NPART-th
+// term of its two sums (the NPART partials then added in a fixed order), so a single tile still
+// keeps every wave busy.  The block column is kept in LDS.  The workgroups also write the zeros
+// below the diagonal blocks (the K == 1 ones block column 0 too), so X is the whole
+// upper-triangular inverse.
+template <int P>
+constexpr int cinv_blk_cols()
+{
+    return P >= 8 ? 1 : (P == 4 ? 2 : (P == 2 ? 4 : 8));
+}
+
+struct CInvBlkArgs {
+    const double *U;  // tile t at U + t ustride, ld ldu, plane stride psu
+    long ldu, psu, ustride;
+    const double *Xd;  // diagonal-block inverses: tile t's block I at Xd + (t nbt + I) 32^2, ld 32
+    long dps;
+    double *X;  // tile t at X + t xstride, ld ldx, plane stride psx
+    long ldx, psx, xstride;
+    int tile;
+};
+
+template <int P>
+__global__ __launch_bounds__(kThreads) void k_cinv_blocks(CInvBlkArgs g)
+{
+    constexpr int NB = kInvNB, NCB = cinv_blk_cols<P>(), Q = 2 * P;
+    constexpr int NPART = kThreads / (NB * NCB);
+    static_assert(NPART >= 1 && NB * NCB * NPART == kThreads, "k_cinv_blocks layout");
+    __shared__ double sX[256 * NCB * Q];         // rows 0 .. (K+1) NB - 1 of this workgroup's columns
+    __shared__ double sP[NPART * NB * NCB * Q];  // partial sums
+    __shared__ double sR[NB * NCB * Q];
+    const int tid = threadIdx.x;
+    const int r = tid % NB, c = (tid / NB) % NCB, part = tid / (NB * NCB);
+    const int K = blockIdx.y + 1, t = blockIdx.z;
+    const int cl = blockIdx.x * NCB + c;  // column inside block column K
+    const int col = K * NB + cl;
+    const double *U = g.U + (long)t * g.ustride;
+    double *X = g.X + (long)t * g.xstride;
+    const int nbt = g.tile / NB;
+    auto xd = [&](int I, int row, int k) __attribute__((always_inline)) {
+        return cldm<P>(g.Xd, g.dps, ((long)t * nbt + I) * NB * NB + (long)k * NB + row);
+    };
+    // sum of the NPART partials of entry (r, c), in part order
+    auto combine = [&]() __attribute__((always_inline)) {
+        CAcc<P> a = cacc_zero<P>();
+        for (int q = 0; q < NPART; ++q) {
+            const CV<P> o = clds_ld<P>(&sP[((q * NB + r) * NCB + c) * Q]);
+            acc_add(a.re, o.re);
+            acc_add(a.im, o.im);
+        }
+        return cacc_get(a);
+    };
+    if (part == 0) {
+        const CV<P> v = xd(K, r, cl);
+        clds_st(&sX[((K * NB + r) * NCB + c) * Q], v);
+        cstm(X, g.psx, (long)col * g.ldx + K * NB + r, v);
+        for (int I = K + 1; I < nbt; ++I) cstm(X, g.psx, (long)col * g.ldx + I * NB + r, czero<P>());
+        if (K == 1) {
+            cstm(X, g.psx, (long)cl * g.ldx + r, xd(0, r, cl));
+            for (int I = 1; I < nbt; ++I) cstm(X, g.psx, (long)cl * g.ldx + I * NB + r, czero<P>());
+        }
+    }
+    __syncthreads();
+    for (int I = K - 1; I >= 0; --I) {
+        // R(r, c) = sum over the rows k of block rows I+1 .. K of U(I NB + r, k) X(k, c)
+        {
+            CAcc<P> a = cacc_zero<P>();
+            int nt = 0;
+            for (int k = (I + 1) * NB + part; k < (K + 1) * NB; k += NPART)
+                cacc_fma_step<P, false>(a, cldm<P>(U, g.psu, (long)k * g.ldu + I * NB + r),
+                                        clds_ld<P>(&sX[(k * NCB + c) * Q]), nt++);
+            clds_st(&sP[((part * NB + r) * NCB + c) * Q], cacc_get(a));
+        }
+        __syncthreads();
+        if (part == 0) clds_st(&sR[(r * NCB + c) * Q], combine());
+        __syncthreads();
+        // X_IK(r, c) = -sum_{k >= r} X_II(r, k) R(k, c)
+        {
+            CAcc<P> a = cacc_zero<P>();
+            int nt = 0;
+            for (int k = r + part; k < NB; k += NPART)
+                cacc_fma_step<P, false>(a, xd(I, r, k), clds_ld<P>(&sR[(k * NCB + c) * Q]), nt++);
+            clds_st(&sP[((part * NB + r) * NCB + c) * Q], cacc_get(a));
+        }
+        __syncthreads();
+        if (part == 0) {
+            const CV<P> v = cneg(combine());
+            clds_st(&sX[((I * NB + r) * NCB + c) * Q], v);
+            cstm(X, g.psx, (long)col * g.ldx + I * NB + r, v);
+        }
+        __syncthreads();
     }
 }
 
@@ -1004,6 +1105,36 @@ void cinvert_tiles(const InvArgs &ia, int ntiles, hipStream_t s)
                 dim3(kThreads), s, ia);
 }
 
+
+// X = U^{-1} for ntiles tiles (diagonal from ia.dsup when given): blocked for tiles of 64 columns
+// or more that are a multiple of 32, with Xd (2P planes of 32 * tile * ntiles doubles) for the
+// diagonal blocks' inverses; the tiles must lie on the diagonal of one matrix (tile t at
+// U + t tile (ldu + 1)) or be a single tile.
+template <int P>
+void cinvert_any(const InvArgs &ia, int ntiles, double *Xd, hipStream_t s)
+{
+    if (ia.tile < 64 || ia.tile % kInvNB != 0) {
+        cinvert_tiles<P>(ia, ntiles, s);
+        return;
+    }
+    const int nbt = ia.tile / kInvNB;
+    const long dps = (long)kInvNB * ia.tile * ntiles;
+    InvArgs id = ia;
+    id.ustride = (long)kInvNB * (ia.ldu + 1);
+    id.X = Xd;
+    id.ldx = kInvNB;
+    id.psx = dps;
+    id.xstride = (long)kInvNB * kInvNB;
+    id.tile = kInvNB;
+    cinvert_tiles<P>(id, ntiles * nbt, s);
+    const CInvBlkArgs ib{ia.U, ia.ldu, ia.psu, ia.ustride, Xd, dps, ia.X, ia.ldx, ia.psx, ia.xstride, ia.tile};
+    constexpr int NCB = cinv_blk_cols<P>();
+    double work = 0.0;  // complex md multiply-adds, 4 real ones each
+    for (int K = 1; K < nbt; ++K) work += 4.0 * (K * (K + 1) / 2 + K) * kInvNB * kInvNB * kInvNB;
+    MDLS_LAUNCH("k_cinv_blocks", P, work * ntiles, (k_cinv_blocks<P>), dim3(kInvNB / NCB, nbt - 1, ntiles),
+                dim3(kThreads), s, ib);
+}
+
 // B(kt:m, cols) := (I - Y_k op(T_k) Y_k^H) B(kt:m, cols) for nc columns: S = Y^H B, U = op(T) S,
 // B -= Y U, with op(T) = T^H (the product Q^H and the QR's trailing update)
 template <int P>
@@ -1105,7 +1236,7 @@ int cqr_t(int m, int n, int tile, double *A, int lda, double *T, int ldt, void *
         ia.psx = tps;
         ia.xstride = 0;
         ia.tile = tile;
-        cinvert_tiles<P>(ia, 1, s);
+        cinvert_any<P>(ia, 1, S, s);  // S is free until the update below
         if (jend < n)
             cblock_apply_h<P>(Y, (long)lda, psa, h, tile, T + (long)kt * ldt, (long)ldt, tps, A + (long)jend * lda + kt,
                               (long)lda, psa, n - jend, S, U, sps, s);
@@ -1198,7 +1329,7 @@ void cbacksub_tiles(const CLayout &L, char *w, int n, int tile, const double *R,
     ia.psx = xips;
     ia.xstride = (long)tile * tile;
     ia.tile = tile;
-    cinvert_tiles<P>(ia, N, s);
+    cinvert_any<P>(ia, N, (double *)(w + L.S), s);
     const long yps = n;
     for (int i = N - 1; i >= 0; --i) {
         const long it = (long)i * tile;

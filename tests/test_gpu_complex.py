@@ -88,6 +88,8 @@ CASES = [
     (8, 64, 48, 16),
     (8, 33, 20, 10),
     (8, 544, 64, 32),    # octo double: the first panel taller than the persistent panel's LDS column
+    (4, 200, 128, 64),   # blocked T inversion (64-column tiles), quad double
+    (8, 128, 128, 64),   # blocked T inversion and back-substitution tiles, octo double
     (1, 128, 96, 32),
 ]
 
@@ -210,7 +212,7 @@ def test_cqr_then_capply_qh(M, orc, P, m, n, tile, nrhs):
         assert np.all(tj[1] == 0.0)
 
 
-@pytest.mark.parametrize("P,n,tile", [(2, 96, 32), (4, 64, 16), (8, 40, 8), (2, 256, 256)])
+@pytest.mark.parametrize("P,n,tile", [(2, 96, 32), (4, 64, 16), (8, 40, 8), (2, 256, 256), (4, 192, 64), (8, 128, 128)])
 def test_cbacksub_matches_oracle(M, orc, P, n, tile):
     print("case cbacksub P=%d n=%d tile=%d" % (P, n, tile), flush=True)
     R = mdgen.cmd_uniform(P, n, n, 3200 + n, mdgen.STREAM_A)
