@@ -90,6 +90,7 @@ CASES = [
     (8, 544, 64, 32),    # octo double: the first panel taller than the persistent panel's LDS column
     (4, 200, 128, 64),   # blocked T inversion (64-column tiles), quad double
     (8, 128, 128, 64),   # blocked T inversion and back-substitution tiles, octo double
+    (4, 256, 256, 256),  # one 256-column panel: 256 persistent workgroups, 8 x 32 diagonal blocks
     (1, 128, 96, 32),
 ]
 
