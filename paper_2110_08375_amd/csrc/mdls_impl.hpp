@@ -274,17 +274,24 @@ __device__ __forceinline__ void panel_run(const PanelArgs &g, int bid)
         }
         return gv;
     };
-    // lane l < jj: w_l = sum_{l <= k < jj} T(l, k) g(k, jj) (wave 3)
+    // lane l < jj: w_l = sum_{l <= k < jj} T(l, k) g(k, jj) (wave 3); even and odd k in two
+    // accumulators, so the two halves of the sum overlap
     auto t_w = [&](int jj, const V<P> &gv) __attribute__((always_inline)) {
-        Acc<P> w = acc_zero<P>();
+        Acc<P> w0 = acc_zero<P>(), w1 = acc_zero<P>();
 #pragma unroll
         for (int k = 0; k < W; ++k) {
             if (k < jj) {
                 const V<P> gk = shfl_md(gv, k);
-                if (lane <= k) acc_fma(w, lds_ld<P>(&s_T[(k * W + lane) * P]), gk);
+                if (lane <= k) {
+                    if (k & 1)
+                        acc_fma(w1, lds_ld<P>(&s_T[(k * W + lane) * P]), gk);
+                    else
+                        acc_fma(w0, lds_ld<P>(&s_T[(k * W + lane) * P]), gk);
+                }
             }
         }
-        return acc_get(w);
+        acc_add_acc(w0, w1);
+        return acc_get(w0);
     };
     // T(0:jj, jj) = -beta_jj w, T(jj, jj) = beta_jj, zero below (wave 3)
     auto t_store = [&](int jj, const V<P> &w) __attribute__((always_inline)) {
@@ -386,15 +393,20 @@ __device__ __forceinline__ void panel_run(const PanelArgs &g, int bid)
                 acc_fma(u, ldm<P>(g.Tp, g.tps, (long)i * W + l), lds_ld<P>(&s_gram[(l * W + cc) * P]));
             pair_sum<P, WW, NT, true>(u, s_comb, s_hrow);
         }
+        // even and odd i in two accumulators, so the two halves of the sum overlap
 #pragma unroll
         for (int k = 0; k < R; ++k) {
             const long r = rbase + k * rstride;
             if (r < hh && c < g.wact) {
-                Acc<P> t = acc_from(a[k]);
+                Acc<P> t0 = acc_from(a[k]), t1 = acc_zero<P>();
 #pragma unroll
-                for (int i = 0; i < W; ++i)
-                    acc_fma(t, y_entry<P>(g.Yp, g.lda, g.ps, r, i, (int)hh, W), lds_ld<P>(&s_hrow[(i * W + c) * P]));
-                a[k] = acc_get(t);
+                for (int i = 0; i < W; i += 2) {
+                    acc_fma(t0, y_entry<P>(g.Yp, g.lda, g.ps, r, i, (int)hh, W), lds_ld<P>(&s_hrow[(i * W + c) * P]));
+                    acc_fma(t1, y_entry<P>(g.Yp, g.lda, g.ps, r, i + 1, (int)hh, W),
+                            lds_ld<P>(&s_hrow[((i + 1) * W + c) * P]));
+                }
+                acc_add_acc(t0, t1);
+                a[k] = acc_get(t0);
             }
         }
         __syncthreads();
