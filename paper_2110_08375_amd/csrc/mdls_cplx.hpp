@@ -15,7 +15,9 @@
 // e^{i theta} mu; sigma = 0 gives beta = 0 and R_jj = x1.  H = I - beta v v^H is Hermitian.
 //
 // Kernels (one QR panel of b = tile columns at a time):
-//   k_crefl   -- the reflector of the panel's first column (one workgroup);
+//   k_cpanel  -- the whole panel in one persistent launch, one workgroup per column, each
+//                column handed to the later ones through device memory behind a counter;
+//   k_crefl   -- (the panel a launch per column instead) the reflector of its first column;
 //   k_cstep   -- for panel column j: H_j applied to the panel columns right of j, one
 //                workgroup per column; workgroup 0 then forms the reflector of column j+1
 //                from the column it has just updated, so one launch per column carries the
@@ -25,6 +27,8 @@
 //   k_cinvert -- T = (diag(1/beta) + triu(G, 1))^{-1} column-parallel, with the diagonal of
 //                the inverse supplied as beta (so beta_j = 0 gives a zero row and column, the
 //                identity reflector); also the diagonal tiles of R for the back substitution;
+//                for tiles of 64 columns or more only their 32 x 32 diagonal blocks, and
+//   k_cinv_blocks -- the blocks above those diagonal blocks, by block rows;
 //   k_ctn, k_ctrmm_h, k_cnn_sub -- the trailing update C := (I - Y T^H Y^H) C, which is the
 //                paper's C + Y W^H C with W = -Y T, and the same for Q^H B;
 //   k_cbs_xi, k_cbs_upd -- x_i := U_i^{-1} b_i and b_j -= A_{j,i} x_i;
