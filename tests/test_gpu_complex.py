@@ -91,6 +91,7 @@ CASES = [
     (4, 200, 128, 64),   # blocked T inversion (64-column tiles), quad double
     (8, 128, 128, 64),   # blocked T inversion and back-substitution tiles, octo double
     (4, 256, 256, 256),  # one 256-column panel: 256 persistent workgroups, 8 x 32 diagonal blocks
+    (4, 900, 32, 16),    # quad double persistent panels of 900 and 884 rows (four rows per thread)
     (1, 128, 96, 32),
 ]
 
