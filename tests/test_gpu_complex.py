@@ -2,7 +2,8 @@
 Section 4, Table 5: complex double double QR of dimension 512 for tiles 32..256) through
 the C ABI against the complex CPU oracle, element by element on seeded inputs.
 
-Tolerance: ||x_gpu - x_or|| / ||x_or|| <= TOL[P] * max(1, kappa_2(A)) as for real data;
+Tolerance: ||x_gpu - x_or|| / ||x_or|| <= TOL[P] * max(1, kappa_2(A)) as for real data, and
+the tight bound 64 n u_P kappa of the real full-size tests;
 R, the Householder vectors and Q^H b against the oracle's at TOL[P] * max(1, kappa) relative
 to the largest entry (the factors are unique once the phase convention of the diagonal is
 fixed, which both sides share).
@@ -71,8 +72,16 @@ def lower(F, n):
     return out
 
 
-def report(case, err, bound):
-    print("%s err=%.3e bound=%.3e" % (case, err, bound), flush=True)
+def unit(P):
+    """u_P = 2^-(53P - (P - 1)) (the tolerance unit of each precision)"""
+    return 2.0 ** -(53 * P - (P - 1))
+
+
+def report(case, err, bound, uk=None):
+    if uk:
+        print("%s err=%.3e bound=%.3e (%.2f u kappa)" % (case, err, bound, err / uk), flush=True)
+    else:
+        print("%s err=%.3e bound=%.3e" % (case, err, bound), flush=True)
 
 
 CASES = [
@@ -173,19 +182,14 @@ def check_csolve(M, orc, P, m, n, tile):
     assert int(info.item()) == 0
     k = kappa(A)
     bound = TOL[P] * max(1.0, k)
-    err = cerr(x.cpu().numpy(), ref["x"])
-    report("x", err, bound)
-    assert err <= bound
+    uk = unit(P) * k
+    tight = 64 * n * uk  # the tight bound of the real path's full-size tests
     Fg = Ag.cpu().numpy()
-    e = cerr(upper(Fg, n), upper(ref["F"], n))
-    report("R", e, bound)
-    assert e <= bound
-    e = cerr(lower(Fg, n), lower(ref["F"], n))
-    report("V", e, bound)
-    assert e <= bound
-    e = cerr(bg.cpu().numpy(), ref["qhb"])
-    report("Q^H b", e, bound)
-    assert e <= bound
+    for name, e in (("x", cerr(x.cpu().numpy(), ref["x"])), ("R", cerr(upper(Fg, n), upper(ref["F"], n))),
+                    ("V", cerr(lower(Fg, n), lower(ref["F"], n))), ("Q^H b", cerr(bg.cpu().numpy(), ref["qhb"]))):
+        report(name, e, bound, uk)
+        assert e <= bound
+        assert e <= tight
 
 
 @pytest.mark.parametrize("P,m,n,tile,nrhs", [(2, 96, 64, 16, 3), (4, 80, 48, 16, 70), (8, 48, 32, 8, 2)])
@@ -273,18 +277,17 @@ def test_table5_complex_dd_512(M, orc):
     ref = orc.clstsq(A, b)
     k = kappa(A)
     bound = TOL[P] * max(1.0, k)
+    uk = unit(P) * k
     for tile in (128, 32, 64, 256):
         print("  tile %d" % tile, flush=True)
         Ag, bg = to_gpu(A), to_gpu(b)
         x, info = M.csolve(P, Ag, bg, tile)
         torch.cuda.synchronize()
         assert int(info.item()) == 0
-        e = cerr(x.cpu().numpy(), ref["x"])
-        report("x tile %d" % tile, e, bound)
-        assert e <= bound
-        e = cerr(upper(Ag.cpu().numpy(), n), upper(ref["F"], n))
-        report("R tile %d" % tile, e, bound)
-        assert e <= bound
+        for name, e in (("x", cerr(x.cpu().numpy(), ref["x"])), ("R", cerr(upper(Ag.cpu().numpy(), n), upper(ref["F"], n)))):
+            report("%s tile %d" % (name, tile), e, bound, uk)
+            assert e <= bound
+            assert e <= 64 * n * uk
 
 
 def test_csolve_graph_replay(M, orc):
