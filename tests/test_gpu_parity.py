@@ -4,9 +4,9 @@ on seeded synthetic inputs.
 Tolerance (forward error of x): ||x_gpu - x_ref|| / ||x_ref|| <= TOL[P] * max(1, kappa_2(A)),
 with TOL = 1e-28 (dd), 1e-58 (qd), 1e-118 (od) and kappa_2 from the leading limbs in FP64.
 The unit roundoffs are 2^-105, 2^-209 and 2^-417, so the tolerance leaves room for the
-O(n) growth of rounding errors in QR and back substitution.  Beside it, the headline-size
-comparisons apply a tight bound, err <= 64 n u_P kappa (u_P = 2^-(53P - P + 1)), which a loss
-of 20 low-order bits anywhere in the path would break, and print err / (u_P kappa).
+O(n) growth of rounding errors in QR and back substitution.  Beside it, the oracle comparisons
+apply a tight bound, err <= 64 n u_P kappa (u_P = 2^-(53P - P + 1)), which a loss of 20
+low-order bits anywhere in the path would break, and print err / (u_P kappa).
 """
 import os
 
@@ -87,9 +87,11 @@ def test_solve_matches_oracle(M, orc, P, m, n, tile, ones):
     assert int(info.item()) == 0
     xg = x.cpu().numpy()
     k = kappa(A)
+    tight = 64 * n * unit(P) * k  # beside the contract, the tight bound of the full-size tests
     err = md_err(xg, ref["x"])
     report("x", err, TOL[P] * max(1, k))
     assert err <= TOL[P] * max(1.0, k)
+    assert err <= tight
     # R (upper triangle of the factored A) against the oracle's R
     Fg = Ag.cpu().numpy()
     Rg = np.stack([np.triu(Fg[l].T[:n, :]) for l in range(P)])
@@ -97,10 +99,15 @@ def test_solve_matches_oracle(M, orc, P, m, n, tile, ones):
     dR = np.zeros_like(Rg[0])
     for l in range(P - 1, -1, -1):
         dR = dR + (Rg[l] - Ro[l])
-    assert np.max(np.abs(dR)) <= TOL[P] * max(1, k) * np.max(np.abs(Ro[0]))
+    eR = np.max(np.abs(dR)) / np.max(np.abs(Ro[0]))
+    assert eR <= TOL[P] * max(1, k)
+    assert eR <= tight
     # Q^T b against the oracle (the part below n carries the residual)
     qerr = md_err(bg.cpu().numpy(), ref["qtb"])
     assert qerr <= TOL[P] * max(1, k)
+    assert qerr <= tight
+    print("  x %.2f, R %.2f, Q^T b %.2f u kappa" % (err / (unit(P) * k), eR / (unit(P) * k), qerr / (unit(P) * k)),
+          flush=True)
 
 
 @pytest.fixture
