@@ -14,6 +14,11 @@ pytestmark = pytest.mark.gpu
 TOL = {2: 1e-28, 4: 1e-58}
 
 
+def unit(P):
+    """u_P = 2^-(53P - (P - 1)); beside TOL every x is also held to the tight bound 64 n u_P kappa"""
+    return 2.0 ** -(53 * P - (P - 1))
+
+
 def dev():
     assert torch.cuda.is_available(), "GPU tests need a GPU"
     return torch.device("cuda:0")
@@ -80,6 +85,7 @@ def test_batched_matches_oracle(M, orc, P):
         for k in range(len(shapes)):
             err = md_err(x_of(M, descs, xg, P, k), refs[k])
             assert err <= TOL[P] * max(1.0, kap[k]), (v, k, shapes[k], err)
+            assert err <= 64 * shapes[k][1] * unit(P) * max(1.0, kap[k]), (v, k, shapes[k], err)
         outs.append(xg)
     xg, _ = run_batch(M, P, descs, A, b, x_len, 0, ws)
     assert np.array_equal(xg, outs[0])  # run to run, bit for bit
@@ -135,9 +141,11 @@ def test_batched_full_size_recovers_ones(M, orc, P):
         err = md_err(x_of(M, descs, xh, P, k), ones)
         worst = max(worst, err / max(1.0, kap))
         assert err <= TOL[P] * max(1.0, kap), (k, m, n, err, kap)
+        assert err <= 64 * n * unit(P) * max(1.0, kap), (k, m, n, err, kap)
     t = times.cpu().numpy().reshape(-1, 2)
     assert np.all(t[:, 1] > t[:, 0])
-    print("batched P=%d: worst err/kappa %.3e, %.1f solves/s" % (P, worst, 512 / (min(ms) * 1e-3)), flush=True)
+    print("batched P=%d: worst err/kappa %.3e (%.2f u), %.1f solves/s" % (P, worst, worst / unit(P), 512 / (min(ms) * 1e-3)),
+          flush=True)
 
 
 def test_batched_graph_replay(M):
