@@ -65,12 +65,14 @@ def test_refined_recovers_x_true(M, orc, P, m, n, tile, iters):
     err = md_err(x.cpu().numpy(), xt)
     nr = steps_taken(norms)
     rel = nr[:, 0] / nr[:, 1]
-    print("refined P=%d err %.3e kappa %.3e steps %d corrections %s" % (P, err, kap, len(nr), rel), flush=True)
+    u = 2.0 ** -(53 * P - (P - 1))
+    print("refined P=%d err %.3e (%.2f u kappa) kappa %.3e steps %d corrections %s"
+          % (P, err, err / (u * kap), kap, len(nr), rel), flush=True)
     assert err <= TOL[P] * max(1.0, kap)
+    assert err <= 64 * n * u * max(1.0, kap)  # the tight bound of the plain path's oracle tests
     assert 3 <= len(nr) < iters  # stopped on the norms, not on the limit
     assert rel[1] < 1e-12 * rel[0] and rel[2] < rel[1]  # the corrections shrink geometrically
     # the stopping rule: the last step's correction, or its contraction estimate, is below u
-    u = 2.0 ** -(53 * P - (P - 1))
     assert rel[-1] <= u or rel[-1] * (nr[-1, 0] / nr[-2, 0]) <= u
 
 
@@ -102,9 +104,12 @@ def test_refined_inconsistent_matches_oracle(M, orc, P, m, n, tile):
     err = md_err(x.cpu().numpy(), xo)
     nr = steps_taken(norms)
     bound = TOL[P] * kap * (1.0 + kap * rho)
-    print("refined inconsistent P=%d err vs oracle %.3e bound %.3e kappa %.3e rho %.3e steps %d"
-          % (P, err, bound, kap, rho, len(nr)), flush=True)
+    u = 2.0 ** -(53 * P - (P - 1))
+    tight = 64 * n * u * kap * (1.0 + kap * rho)
+    print("refined inconsistent P=%d err vs oracle %.3e bound %.3e (%.2f u kappa (1 + kappa rho)) kappa %.3e rho %.3e "
+          "steps %d" % (P, err, bound, err / (u * kap * (1.0 + kap * rho)), kap, rho, len(nr)), flush=True)
     assert err <= bound
+    assert err <= tight
     assert len(nr) < 12
 
 
