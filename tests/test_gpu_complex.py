@@ -234,8 +234,9 @@ def test_cbacksub_matches_oracle(M, orc, P, n, tile):
     assert int(dinfo.item()) == 0
     k = float(np.linalg.cond(R[0, 0].T + 1j * R[1, 0].T))
     e = cerr(x.cpu().numpy(), xo)
-    report("x", e, TOL[P] * k)
+    report("x", e, TOL[P] * k, unit(P) * k)
     assert e <= TOL[P] * max(1.0, k)
+    assert e <= 64 * n * unit(P) * max(1.0, k)
 
 
 def test_cbacksub_zero_diagonal_info(M):

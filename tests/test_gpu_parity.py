@@ -211,6 +211,9 @@ def test_backsub_matches_oracle(M, orc, P, n, tile):
     err = md_err(x.cpu().numpy(), xo)
     report("bs", err, TOL[P])
     assert err <= TOL[P] * 10
+    k = float(np.linalg.cond(R[0].T))
+    print("  %.2f u kappa (kappa %.2f)" % (err / (unit(P) * k), k), flush=True)
+    assert err <= 64 * n * unit(P) * k
 
 
 def test_zero_diagonal_sets_info(M):
