@@ -86,6 +86,18 @@ def measured_fp64():
     return d if d.get("sources_sha256") == sources_digest() else None
 
 
+def hw_flops_per_launch(hw, kernel):
+    """Hardware FP64 flops per launch of `kernel` from measured_fp64()'s summary, or None."""
+    pl = hw["per_launch"].get(kernel) if kernel else None
+    return None if pl is None else pl["hw_flops"]
+
+
+def hw_flops_per_solve(hw, prec_name):
+    """Hardware FP64 flops of one solve in precision `prec_name` ("dd", "qd", "od"), or None."""
+    ps = hw["per_solve"].get(prec_name)
+    return None if ps is None else ps["hw_flops"]
+
+
 def cpu_baseline(sample, threads):
     """The CPU oracle (unchanged) on a bounded sample of square least-squares solves with the
     benchmark's input recipe; Table-1 double ops per second, blended and per precision."""
@@ -576,12 +588,12 @@ def main():
         hw = measured_fp64()
         if hw is not None:
             for lab, key in ((label, None), (roof.get("throughput_kernel", {}).get("kernel"), "throughput_kernel")):
-                pl = hw["per_launch"].get(lab) if lab else None
-                if pl is None:
+                fl = hw_flops_per_launch(hw, lab)
+                if fl is None:
                     continue
                 tgt = roof if key is None else roof[key]
                 us = tgt["avg_launch_us"]
-                tgt["hw_achieved"] = round(pl["flops"] / (us * 1e-6) / 1e12, 4)
+                tgt["hw_achieved"] = round(fl / (us * 1e-6) / 1e12, 4)
                 tgt["hw_frac"] = round(tgt["hw_achieved"] / peak, 5)
             roof["hw_source"] = "profiles/fp64_insts_ls_n1024.json"
         log("dominant kernel %s: %.3f ms over %d launches, %.3f TFLOP/s" % (label, ms, cnt, achieved))
@@ -598,9 +610,9 @@ def main():
     hw = measured_fp64()
     if hw is not None:
         for P in precs:
-            ps = hw["per_solve"].get(PNAME[P])
-            if ps is not None:
-                t = ps["flops"] / (per_prec[PNAME[P]]["ms"] * 1e-3) / 1e12
+            fl = hw_flops_per_solve(hw, PNAME[P])
+            if fl is not None:
+                t = fl / (per_prec[PNAME[P]]["ms"] * 1e-3) / 1e12
                 per_prec[PNAME[P]]["hardware_tflops"] = round(t, 4)
                 per_prec[PNAME[P]]["hardware_frac"] = round(t / peak, 5)
 
