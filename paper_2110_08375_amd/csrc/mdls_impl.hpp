@@ -73,7 +73,8 @@ __device__ inline void grid_sync(unsigned *ctr, unsigned target, int *err, unsig
     const int lane = threadIdx.x & 63;
     // the fence before the relaxed arrival releases this workgroup's stores; the relaxed
     // polls need no cache invalidation each, the fence after them acquires the others' stores
-    __threadfence();
+    // (a release and an acquire fence: neither side needs the other half of a full fence)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     if (lane == 0) {
         __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         unsigned spins = 0;
@@ -85,7 +86,7 @@ __device__ inline void grid_sync(unsigned *ctr, unsigned target, int *err, unsig
             }
         }
     }
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }
 
 // Sum over a workgroup of per-thread partials of WW pairs: thread t holds a partial of pair
