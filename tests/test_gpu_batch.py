@@ -109,6 +109,36 @@ def test_batched_zero_column_sets_info(M):
 
 
 @pytest.mark.parametrize("P", (2, 4))
+def test_batched_nan_problem_is_isolated(M, P):
+    """A NaN in one problem's A: that problem's x holds NaN with info 0 (NaN is not an exact
+    zero), every kernel exits, and every other problem's x equals the clean batch's bit for bit
+    in each kernel variant (teams share no values across problems)."""
+    shapes = [(40, 12), (64, 32), (30, 30), (96, 17), (50, 5), (8, 8)]
+
+    def rhs(k, Ak):
+        return mdgen.md_vector(P, Ak.shape[2], 11 + k, 3)
+
+    descs, A, b, x_len, _ = make_batch(M, P, shapes, 120 + P, rhs)
+    An = A.copy()
+    d = descs[1]
+    An[d.a_off + 3 * 64 + 5] = np.nan  # problem 1, leading limb, column 3, row 5
+    ws = M.batch_workspace(P, len(shapes), dev())
+    M.batch_plan(P, descs, ws)
+    for v in range(M.batch_variants(P)):
+        print("case batched nan P=%d variant %d" % (P, v), flush=True)
+        xc, ic = run_batch(M, P, descs, A, b, x_len, v, ws)
+        xn, inn = run_batch(M, P, descs, An, b, x_len, v, ws)
+        assert np.all(ic == 0) and np.all(inn == 0), (v, ic, inn)
+        assert np.isfinite(xc).all()
+        for k in range(len(shapes)):
+            xk = x_of(M, descs, xn, P, k)
+            if k == 1:
+                assert np.isnan(xk).any(), v
+            else:
+                assert np.array_equal(xk, x_of(M, descs, xc, P, k)), (v, k)
+
+
+@pytest.mark.parametrize("P", (2, 4))
 def test_batched_full_size_recovers_ones(M, orc, P):
     """512 problems, m uniform in [32, 512], n uniform in [16, m] (the batched workload), b = A ones
     formed exactly by the oracle: every x must be ones within TOL * kappa; the autotuner's choice

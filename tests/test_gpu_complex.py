@@ -171,6 +171,38 @@ def test_cpanel_wait_timeout(M, orc, tuning):
     assert np.all(np.isfinite(x.cpu().numpy()))
 
 
+@pytest.mark.parametrize("P", (2, 4, 8))
+def test_cnan_input_propagates(M, tuning, P):
+    """A NaN in A comes out as NaN in x through both panel forms (one launch per column, and the
+    persistent panel whose hand-off counts arrivals, not values): every kernel exits, info stays
+    0 (NaN is not an exact zero), and the next solve on the same stream is finite.  The same for
+    a NaN in R given to the back substitution."""
+    from paper_2110_08375_amd import mdls
+
+    m, n, tile = 300, 96, 32
+    A, _ = mdgen.cls_problem(P, m, n, 3900 + P)
+    b = mdgen.cmd_vector(P, m, 3900 + P, mdgen.STREAM_B)
+    An = A.copy()
+    An[0, 0, 3, 5] = np.nan
+    for cp in (0, 1):
+        print("case cnan P=%d m=%d n=%d tile=%d cpanel=%d" % (P, m, n, tile, cp), flush=True)
+        tuning(mdls.MDLS_TUNE_CPANEL, cp)
+        x, info = M.csolve(P, to_gpu(An), to_gpu(b), tile)
+        torch.cuda.synchronize()
+        assert int(info.item()) == 0
+        assert np.isnan(x.cpu().numpy()).any()
+        x2, info2 = M.csolve(P, to_gpu(A), to_gpu(b), tile)
+        torch.cuda.synchronize()
+        assert int(info2.item()) == 0
+        assert np.isfinite(x2.cpu().numpy()).all()
+    R = mdgen.cmd_uniform(P, n, n, 3950 + P, mdgen.STREAM_A)
+    R[1, 0, 70, 20] = np.nan  # imaginary part of R(20, 70), above the diagonal
+    y, info3 = M.cbacksub(P, to_gpu(R), to_gpu(mdgen.cmd_vector(P, n, 3950 + P, mdgen.STREAM_B)), tile)
+    torch.cuda.synchronize()
+    assert int(info3.item()) == 0
+    assert np.isnan(y.cpu().numpy()).any()
+
+
 def check_csolve(M, orc, P, m, n, tile):
     print("case csolve P=%d m=%d n=%d tile=%d" % (P, m, n, tile), flush=True)
     A, _ = mdgen.cls_problem(P, m, n, 3000 + m + n)
